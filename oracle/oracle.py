@@ -1,0 +1,397 @@
+"""FP64 CPU oracle: Python side.
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline
+leg of bench.py import this module.  It shares no code with the GPU library
+(paper_2503_07898_amd/) and never imports it.
+
+Contents
+  * ctypes binding of lbm_oracle.c (the D3Q19 solver, see that file's header);
+  * the reference builder of the disaggregated index maps (block ids, Morton
+    order per group, neighbour tables, canonical order), written as a direct
+    coordinate search (sections "Disaggregation on a Sparse Domain" and
+    "Disaggregated Design Method": classify, then map each group with a
+    locality order; space-filling-curve managed blocks);
+  * small helpers (relative L2 error).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "lbm_oracle.c")
+Q = 19
+
+# face ids and boundary kinds of the oracle (its own numbering)
+XMIN, XMAX, YMIN, YMAX, ZMIN, ZMAX = range(6)
+BB, MOVING, REG_VEL, REG_PRES = range(4)
+BGK, REGULARIZED = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile lbm_oracle.c with gcc (-O3 -fopenmp) into liboracle.so."""
+    if force or not os.path.exists(LIB_PATH) or (
+        os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH)
+    ):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+             "-Wall", "-Wextra", "-o", tmp, SRC_PATH, "-lm"]
+        )
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("periodic", ctypes.c_int32 * 3),
+        ("fluid", ctypes.POINTER(ctypes.c_uint8)),
+        ("bc_kind", ctypes.c_int32 * 6),
+        ("bc_val", (ctypes.c_double * 3) * 6),
+        ("tau", ctypes.c_double),
+        ("collision", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        gp = ctypes.POINTER(_Grid)
+        L.orc_step.argtypes = [gp, dp, dp]
+        L.orc_run.argtypes = [gp, dp, dp, ctypes.c_int32]
+        L.orc_step_voxels.argtypes = [gp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
+        L.orc_init_equilibrium.argtypes = [gp, dp, dp, dp]
+        L.orc_init_equilibrium.restype = None
+        L.orc_macroscopic.argtypes = [gp, dp, dp, dp]
+        L.orc_macroscopic.restype = None
+        L.orc_lattice.argtypes = [ctypes.POINTER(ctypes.c_int32), dp, ctypes.POINTER(ctypes.c_int32)]
+        L.orc_lattice.restype = None
+        L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
+        L.orc_equilibrium.restype = None
+        L.orc_moments.argtypes = [dp, dp, dp]
+        L.orc_moments.restype = None
+        L.orc_collide_bgk.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_collide_bgk.restype = None
+        L.orc_collide_regularized.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_collide_regularized.restype = None
+        L.orc_f1.argtypes = [dp, dp, dp]
+        L.orc_f1.restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lattice():
+    """(c [19,3] int, w [19] float64, opp [19] int) as the oracle defines them."""
+    c = np.zeros((Q, 3), np.int32)
+    w = np.zeros(Q, np.float64)
+    opp = np.zeros(Q, np.int32)
+    lib().orc_lattice(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(w),
+                      opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return c, w, opp
+
+
+def equilibrium(rho: float, u) -> np.ndarray:
+    u = np.ascontiguousarray(u, np.float64)
+    out = np.zeros(Q)
+    lib().orc_equilibrium(float(rho), _dp(u), _dp(out))
+    return out
+
+
+def moments(f) -> tuple[float, np.ndarray]:
+    f = np.ascontiguousarray(f, np.float64)
+    r = np.zeros(1)
+    u = np.zeros(3)
+    lib().orc_moments(_dp(f), _dp(r), _dp(u))
+    return float(r[0]), u
+
+
+def collide_bgk(f, tau: float) -> np.ndarray:
+    f = np.ascontiguousarray(f, np.float64)
+    out = np.zeros(Q)
+    lib().orc_collide_bgk(_dp(f), float(tau), _dp(out))
+    return out
+
+
+def collide_regularized(f, tau: float) -> np.ndarray:
+    f = np.ascontiguousarray(f, np.float64)
+    out = np.zeros(Q)
+    lib().orc_collide_regularized(_dp(f), float(tau), _dp(out))
+    return out
+
+
+def f1_projection(f, feq) -> np.ndarray:
+    f = np.ascontiguousarray(f, np.float64)
+    feq = np.ascontiguousarray(feq, np.float64)
+    out = np.zeros(Q)
+    lib().orc_f1(_dp(f), _dp(feq), _dp(out))
+    return out
+
+
+@dataclass
+class Grid:
+    """A single-resolution voxel box for the oracle.
+
+    fluid: uint8 array shaped (nz, ny, nx) (x fastest in memory) or None.
+    bc: per face (XMIN..ZMAX) a (kind, value3) pair; ignored on periodic axes.
+    """
+    nx: int
+    ny: int
+    nz: int
+    periodic: tuple = (True, True, True)
+    fluid: np.ndarray | None = None
+    bc: list = field(default_factory=lambda: [(BB, (0.0, 0.0, 0.0))] * 6)
+    tau: float = 0.6
+    collision: int = BGK
+
+    def _struct(self):
+        g = _Grid()
+        g.nx, g.ny, g.nz = self.nx, self.ny, self.nz
+        for a in range(3):
+            g.periodic[a] = 1 if self.periodic[a] else 0
+        if self.fluid is not None:
+            fl = np.ascontiguousarray(self.fluid, np.uint8)
+            assert fl.shape == (self.nz, self.ny, self.nx)
+            self._fluid_keep = fl
+            g.fluid = fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        else:
+            g.fluid = ctypes.POINTER(ctypes.c_uint8)()
+        for k in range(6):
+            kind, val = self.bc[k]
+            g.bc_kind[k] = int(kind)
+            for a in range(3):
+                g.bc_val[k][a] = float(val[a]) if a < len(val) else 0.0
+        g.tau = float(self.tau)
+        g.collision = int(self.collision)
+        return g
+
+    @property
+    def nvox(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def fluid_mask(self) -> np.ndarray:
+        if self.fluid is None:
+            return np.ones((self.nz, self.ny, self.nx), bool)
+        return np.asarray(self.fluid, bool)
+
+    def init_equilibrium(self, rho, u) -> np.ndarray:
+        """rho (nz,ny,nx), u (nz,ny,nx,3) -> f (nz,ny,nx,19)."""
+        rho = np.ascontiguousarray(np.broadcast_to(rho, (self.nz, self.ny, self.nx)), np.float64)
+        u = np.ascontiguousarray(np.broadcast_to(u, (self.nz, self.ny, self.nx, 3)), np.float64)
+        f = np.zeros((self.nz, self.ny, self.nx, Q))
+        g = self._struct()
+        lib().orc_init_equilibrium(ctypes.byref(g), _dp(rho), _dp(u), _dp(f))
+        return f
+
+    def step(self, f: np.ndarray) -> np.ndarray:
+        out = np.zeros_like(f)
+        g = self._struct()
+        r = lib().orc_step(ctypes.byref(g), _dp(f), _dp(out))
+        if r != 0:
+            raise ValueError("oracle: a link crosses two regularized faces")
+        return out
+
+    def run(self, f: np.ndarray, nsteps: int) -> np.ndarray:
+        f = np.array(f, np.float64, order="C", copy=True)
+        work = np.zeros_like(f)
+        g = self._struct()
+        r = lib().orc_run(ctypes.byref(g), _dp(f), _dp(work), int(nsteps))
+        if r != 0:
+            raise ValueError("oracle: a link crosses two regularized faces")
+        return f
+
+    def step_voxels(self, f: np.ndarray, vox: np.ndarray) -> np.ndarray:
+        vox = np.ascontiguousarray(vox, np.int64)
+        out = np.zeros((len(vox), Q))
+        g = self._struct()
+        r = lib().orc_step_voxels(ctypes.byref(g), _dp(f),
+                                  vox.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  len(vox), _dp(out))
+        if r != 0:
+            raise ValueError("oracle: a link crosses two regularized faces")
+        return out
+
+    def macroscopic(self, f: np.ndarray):
+        rho = np.zeros((self.nz, self.ny, self.nx))
+        u = np.zeros((self.nz, self.ny, self.nx, 3))
+        g = self._struct()
+        lib().orc_macroscopic(ctypes.byref(g), _dp(f), _dp(rho), _dp(u))
+        return rho, u
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.sqrt(np.sum(b * b))
+    return float(np.sqrt(np.sum((a - b) ** 2)) / den) if den > 0 else float(np.sqrt(np.sum(a * a)))
+
+
+# ------------------------------------------------------- index-map builder ---
+# Reference builder of the disaggregated block layout, written as a direct
+# coordinate search with no hashing.  Conventions (readings of the paper's
+# "classify, then map each group with a locality order" and "blocks managed by
+# a space-filling curve"):
+#   * 4^3-voxel blocks; a block is active if it holds a fluid voxel;
+#   * dense grids: the boundary group is every block that touches a
+#     non-periodic box face (shell versus interior);
+#   * block-sparse grids: the boundary group is every block holding a voxel
+#     next to a moving-wall or regularized face (voxels needing the heavy
+#     boundary treatment); bounce-back voxels stay in the non-boundary group;
+#   * the non-boundary group is split into "masked" blocks (some voxel pulls
+#     from a non-fluid source) and "full" blocks (all 18 neighbours active
+#     and every voxel of the 3x3x3-block neighbourhood used by D3Q19 is fluid);
+#   * group order [boundary | masked | full]; ascending Morton key in each
+#     group, key bits interleaved x at 3b, y at 3b+1, z at 3b+2;
+#   * voxel-in-block order x + 4y + 16z;
+#   * neighbour table in direction order 1..18 of the oracle's lattice, -1 if
+#     the neighbour block is inactive or outside a non-periodic box.
+
+def morton_key(bx: int, by: int, bz: int) -> int:
+    k = 0
+    for b in range(21):
+        k |= ((bx >> b) & 1) << (3 * b)
+        k |= ((by >> b) & 1) << (3 * b + 1)
+        k |= ((bz >> b) & 1) << (3 * b + 2)
+    return k
+
+
+def _face_voxel_kinds(nx, ny, nz, periodic, face_kinds, heavy):
+    """Boolean (nz,ny,nx): voxels next to a non-periodic face of a kind in `heavy`."""
+    m = np.zeros((nz, ny, nx), bool)
+    n = (nx, ny, nz)
+    for face in range(6):
+        axis, side = face // 2, face % 2
+        if periodic[axis] or face_kinds[face] not in heavy:
+            continue
+        idx = [slice(None)] * 3
+        idx[2 - axis] = n[axis] - 1 if side else 0
+        m[tuple(idx)] = True
+    return m
+
+
+def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool):
+    """Returns a dict with coords [nb,3], nbr [nb,18], fmask [nb] (uint64),
+    groups (n_boundary, n_masked, n_full), canon [nb*64] (int64, -1 = not
+    fluid), n_fluid."""
+    c, _, _ = lattice()
+    B = 4
+    assert nx % B == 0 and ny % B == 0 and nz % B == 0
+    nbx, nby, nbz = nx // B, ny // B, nz // B
+    fl = np.ones((nz, ny, nx), bool) if fluid is None else np.asarray(fluid, bool)
+    heavy = _face_voxel_kinds(nx, ny, nz, periodic, face_kinds, (MOVING, REG_VEL, REG_PRES))
+
+    def block_view(a, bx, by, bz):
+        return a[bz * B:(bz + 1) * B, by * B:(by + 1) * B, bx * B:(bx + 1) * B]
+
+    active = {}
+    for bz in range(nbz):
+        for by in range(nby):
+            for bx in range(nbx):
+                if block_view(fl, bx, by, bz).any():
+                    active[(bx, by, bz)] = True
+
+    def neighbour(bx, by, bz, d):
+        q = [bx + c[d, 0], by + c[d, 1], bz + c[d, 2]]
+        nb = (nbx, nby, nbz)
+        for a in range(3):
+            if q[a] < 0 or q[a] >= nb[a]:
+                if not periodic[a]:
+                    return None
+                q[a] %= nb[a]
+        return tuple(q) if tuple(q) in active else None
+
+    def group_of(bx, by, bz):
+        if dense:
+            shell = ((not periodic[0] and (bx == 0 or bx == nbx - 1)) or
+                     (not periodic[1] and (by == 0 or by == nby - 1)) or
+                     (not periodic[2] and (bz == 0 or bz == nbz - 1)))
+            if shell:
+                return 0
+        elif block_view(heavy & fl, bx, by, bz).any():
+            return 0
+        # full: every source of every voxel in the block is a fluid voxel
+        full = block_view(fl, bx, by, bz).all()
+        for d in range(1, 19):
+            nbk = neighbour(bx, by, bz, d)
+            if nbk is None or not block_view(fl, *nbk).all():
+                full = False
+        return 2 if full else 1
+
+    groups = {0: [], 1: [], 2: []}
+    for key in active:
+        groups[group_of(*key)].append(key)
+    order = []
+    for gid in (0, 1, 2):
+        order += sorted(groups[gid], key=lambda k: morton_key(*k))
+    slot_of = {k: s for s, k in enumerate(order)}
+    nb = len(order)
+    coords = np.array(order, np.int32).reshape(nb, 3)
+    nbr = np.full((nb, 18), -1, np.int32)
+    fmask = np.zeros(nb, np.uint64)
+    for s, (bx, by, bz) in enumerate(order):
+        for d in range(1, 19):
+            q = neighbour(bx, by, bz, d)
+            if q is not None:
+                nbr[s, d - 1] = slot_of[q]
+        bits = 0
+        v = block_view(fl, bx, by, bz)
+        for lz in range(B):
+            for ly in range(B):
+                for lx in range(B):
+                    if v[lz, ly, lx]:
+                        bits |= 1 << (lx + 4 * ly + 16 * lz)
+        fmask[s] = np.uint64(bits)
+    # canonical order: fluid voxels, x fastest
+    lin = -np.ones((nz, ny, nx), np.int64)
+    lin[fl] = np.arange(int(fl.sum()), dtype=np.int64)
+    canon = -np.ones(nb * 64, np.int64)
+    for s, (bx, by, bz) in enumerate(order):
+        v = block_view(lin, bx, by, bz)
+        for lz in range(B):
+            for ly in range(B):
+                for lx in range(B):
+                    canon[s * 64 + lx + 4 * ly + 16 * lz] = v[lz, ly, lx]
+    return dict(coords=coords, nbr=nbr, fmask=fmask,
+                groups=tuple(len(groups[g]) for g in (0, 1, 2)),
+                canon=canon, n_fluid=int(fl.sum()))
+
+
+def brute_force_neighbours(coords, periodic, nblocks_axis):
+    """O(n^2) scan: for each block and direction, search every block for the
+    one at the offset (used to pin build_block_maps)."""
+    c, _, _ = lattice()
+    nb = len(coords)
+    out = np.full((nb, 18), -1, np.int32)
+    for s in range(nb):
+        for d in range(1, 19):
+            want = []
+            ok = True
+            for a in range(3):
+                q = int(coords[s, a]) + int(c[d, a])
+                if q < 0 or q >= nblocks_axis[a]:
+                    if not periodic[a]:
+                        ok = False
+                    q %= nblocks_axis[a]
+                want.append(q)
+            if not ok:
+                continue
+            for t in range(nb):
+                if list(coords[t]) == want:
+                    out[s, d - 1] = t
+    return out
