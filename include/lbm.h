@@ -1,0 +1,204 @@
+/*
+ * lbm.h -- C ABI of liblbm.so, a D3Q19 lattice-Boltzmann collide-and-stream
+ * library for AMD Instinct MI355X (gfx950) built around the disaggregated
+ * data-structure design of "Disaggregated Design for GPU-Based Volumetric
+ * Data Structures" (arXiv 2503.07898).
+ *
+ * The paper's method (section "Disaggregated Design Method", Definition 1):
+ * pick properties that matter for a performance objective, classify voxels
+ * into groups by them, map each group to memory with an ordinary locality
+ * order, and run a group-specific operation on each group.  This library
+ * applies it to the three grid kinds of that section:
+ *   - dense grids ("Disaggregation on a Dense Domain"): a shell group of
+ *     blocks that touch a non-periodic box face and an interior group;
+ *   - block-sparse grids of 4^3-voxel blocks ("Disaggregation on a Sparse
+ *     Domain", memory-based grouping): boundary blocks stored first, then
+ *     non-boundary blocks, one kernel per group;
+ *   - multi-resolution grids ("Disaggregation on a Multi-resolution
+ *     Domain"): per level, blocks near a resolution jump and uniform blocks,
+ *     with collide and stream fused on the uniform ones.
+ * The update itself is the LBM of the evaluation section: D3Q19, BGK
+ * collision, halfway bounce-back on obstacles, regularized inflow/outflow
+ * faces, and a moving-wall lid for the lid-driven cavity.
+ *
+ * Conventions shared by every call
+ *   - Every function returns an lbm_status and never aborts.  On failure,
+ *     lbm_last_error() returns a message for the calling thread.
+ *   - The library never allocates device memory and never creates streams.
+ *     The caller allocates one device workspace whose size lbm_grid_commit
+ *     reports and passes it to lbm_grid_bind; it must stay valid until
+ *     lbm_grid_destroy.  Device pointers passed to other calls are caller
+ *     owned as well.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued asynchronously on it; host-side results
+ *     (sizes, index maps) are returned synchronously.
+ *   - Call order: create -> set_boundary* -> commit -> bind -> init or
+ *     write_populations -> step / read / reduce.  Calls made out of order
+ *     return LBM_ERR_STATE.
+ *   - Voxel coordinates: x fastest, then y, then z.  "Canonical order" of a
+ *     level lists its fluid voxels in that lexicographic order of level
+ *     coordinates; every array exchanged with the caller uses it.  The
+ *     internal grouped layout stays private and is exposed only through
+ *     lbm_get_index_map.
+ *   - Lattice direction order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
+ *     7..18 = (+1,+1,0),(-1,-1,0),(+1,-1,0),(-1,+1,0),(+1,0,+1),(-1,0,-1),
+ *     (+1,0,-1),(-1,0,+1),(0,+1,+1),(0,-1,-1),(0,+1,-1),(0,-1,+1).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_INVALID_ARG = -1,
+  LBM_ERR_OUT_OF_MEMORY = -2, /* host allocation failed */
+  LBM_ERR_HIP = -3,           /* a HIP runtime call failed; message holds hipGetErrorString */
+  LBM_ERR_STATE = -4,         /* call out of order */
+  LBM_ERR_UNSUPPORTED = -5,   /* valid request this build does not implement */
+  LBM_ERR_NUMERIC = -6        /* non-finite values found by lbm_check */
+} lbm_status;
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *lbm_last_error(void);
+
+typedef struct lbm_grid lbm_grid; /* opaque host object owned by the library */
+
+typedef enum { LBM_DENSE = 0, LBM_BLOCK_SPARSE = 1, LBM_MULTIRES = 2 } lbm_grid_kind;
+
+/* Population storage.  The shifted forms store h_i = f_i - w_i rounded to
+ * nearest-even in binary16 / bfloat16; arithmetic is FP32 in every form. */
+typedef enum { LBM_F32 = 0, LBM_F16_SHIFTED = 1, LBM_BF16_SHIFTED = 2 } lbm_storage;
+
+/* Collision operator for non-boundary voxels: BGK (evaluation section),
+ * the regularized operator (Hermite projection of the non-equilibrium part,
+ * the same projection the regularized faces use), or a learned MLP closure. */
+typedef enum { LBM_BGK = 0, LBM_REGULARIZED = 1, LBM_MLP = 2 } lbm_collision;
+
+/* LBM_PLAIN_SINGLE_KERNEL: the comparison arm of each grid kind --
+ *   dense: one kernel over a lexicographic structure-of-arrays box;
+ *   block-sparse: the "naive" single kernel (table dissBlock) that carries
+ *     every boundary rule and so the boundary register demand everywhere;
+ *   multires: collision and streaming as separate kernels at every level
+ *     except the finest (the unfused baseline of the multires evaluation).
+ * LBM_DISAGG: the disaggregated groups, one specialized kernel per group. */
+typedef enum { LBM_PLAIN_SINGLE_KERNEL = 0, LBM_DISAGG = 1 } lbm_schedule;
+
+typedef struct {
+  lbm_grid_kind kind;
+  int32_t nx, ny, nz;        /* finest-level box in voxels; block grids need multiples of 4
+                                (multires: of 4 * 2^(num_levels-1)) */
+  uint8_t periodic[3];       /* per axis x, y, z: 1 = periodic */
+  int32_t num_levels;        /* 1 for dense and block-sparse */
+  const uint8_t *fluid_mask; /* host, nx*ny*nz, 1 = fluid, NULL = all fluid.  Dense grids
+                                must be all fluid. Read during create only. */
+  const uint8_t *level_map;  /* multires: host, nx*ny*nz level of each finest voxel
+                                (0 = finest), else NULL. Read during create only. */
+  double tau;                /* relaxation time (multires: of the coarsest level) */
+  lbm_storage storage;
+  lbm_collision collision;
+  lbm_schedule schedule;
+} lbm_grid_desc;
+
+/* Builds the host side of a grid: classification into groups, locality
+ * order per group, index and neighbour tables (Definition 1, steps 2-3).
+ * Errors: LBM_ERR_INVALID_ARG for bad sizes or masks (message says which). */
+lbm_status lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out);
+
+typedef enum { LBM_XMIN = 0, LBM_XMAX, LBM_YMIN, LBM_YMAX, LBM_ZMIN, LBM_ZMAX } lbm_face;
+
+/* Boundary kinds of the evaluation section: halfway bounce-back walls, a
+ * moving-wall lid (lid-driven cavity; value = wall velocity, wall density 1),
+ * and the regularized velocity inlet (value = u) / pressure outlet
+ * (value[0] = density) of the wind-tunnel case.  Every face of a
+ * non-periodic axis defaults to bounce-back.  Solid voxels inside the box are
+ * always bounce-back. */
+typedef enum {
+  LBM_BC_BOUNCE_BACK = 0,
+  LBM_BC_MOVING_WALL = 1,
+  LBM_BC_REG_VELOCITY = 2,
+  LBM_BC_REG_PRESSURE = 3
+} lbm_bc;
+
+lbm_status lbm_set_boundary(lbm_grid *g, lbm_face face, lbm_bc kind, const double value[3]);
+
+/* Finishes classification (the boundary kinds decide the groups of a
+ * block-sparse grid) and reports the device workspace size in bytes.
+ * Errors: LBM_ERR_INVALID_ARG if a voxel would need two regularized faces. */
+lbm_status lbm_grid_commit(lbm_grid *g, size_t *workspace_bytes);
+
+/* Hands the library a device workspace of at least the committed size
+ * (256-byte aligned) and uploads the index tables into it on `stream`. */
+lbm_status lbm_grid_bind(lbm_grid *g, void *workspace, size_t bytes, void *stream);
+
+/* Number of fluid voxels of a level (canonical array length). */
+lbm_status lbm_num_voxels(const lbm_grid *g, int32_t level, int64_t *n);
+
+/* Sets every fluid voxel of `level` to f^eq(rho, u); rho_dev [N] and
+ * u_dev [3][N] are FP64 device arrays in canonical order. */
+lbm_status lbm_init_equilibrium(lbm_grid *g, int32_t level, const double *rho_dev,
+                                const double *u_dev, void *stream);
+
+/* Advances n_steps time steps (multires: coarse steps).  Each step is the
+ * fused pull collide-and-stream of every group, ping-ponging two population
+ * buffers inside the workspace. */
+lbm_status lbm_step(lbm_grid *g, int32_t n_steps, void *stream);
+
+/* Density and velocity of every fluid voxel of `level` in canonical order,
+ * computed in FP64 from the stored post-collision populations.  rho_dev [N],
+ * u_dev [3][N]; out_is_f64 = 1 writes doubles, 0 writes floats. */
+lbm_status lbm_read_macroscopic(lbm_grid *g, int32_t level, void *rho_dev, void *u_dev,
+                                int32_t out_is_f64, void *stream);
+
+/* FP64 reductions over all levels: out5_dev[0] = mass sum f,
+ * [1..3] = momentum sum c f, [4] = kinetic energy sum rho |u|^2 / 2.
+ * Multires levels weight each voxel by its volume 8^level.  Deterministic
+ * (fixed-order two-pass sum). */
+lbm_status lbm_reduce(lbm_grid *g, double *out5_dev, void *stream);
+
+/* Post-collision populations of `level` as FP64 [19][N] in canonical order. */
+lbm_status lbm_read_populations(lbm_grid *g, int32_t level, double *f_dev, void *stream);
+/* Overwrites the populations of `level` from FP64 [19][N] canonical order
+ * (checkpoint restore); values are rounded to the storage format. */
+lbm_status lbm_write_populations(lbm_grid *g, int32_t level, const double *f_dev, void *stream);
+
+/* Index maps of the internal layout, copied to host memory.  Pass
+ * host_out = NULL to query the element count in *count.
+ *   LBM_MAP_GROUPS     int64 [4]: blocks in groups (boundary, masked, full, total)
+ *   LBM_MAP_COORDS     int32 [nblocks][3]: block coordinates, in storage order
+ *   LBM_MAP_NEIGHBOURS int32 [nblocks][18]: slot of the neighbour block in
+ *                      direction 1..18, -1 = none
+ *   LBM_MAP_FLUIDMASK  uint64 [nblocks]: bit x+4y+16z set for fluid voxels
+ *   LBM_MAP_CANONICAL  int64 [nblocks*64]: canonical index of each slot, -1 = not fluid */
+typedef enum {
+  LBM_MAP_GROUPS = 0,
+  LBM_MAP_COORDS = 1,
+  LBM_MAP_NEIGHBOURS = 2,
+  LBM_MAP_FLUIDMASK = 3,
+  LBM_MAP_CANONICAL = 4
+} lbm_map;
+lbm_status lbm_get_index_map(const lbm_grid *g, int32_t level, lbm_map which, void *host_out,
+                             size_t *count);
+
+/* Kernel launches one lbm_step issues per time step, and the blocks each of
+ * them covers (for checking the structure of table dissBlock).  kernels_out
+ * [max] receives block counts per launch; *n receives the launch count. */
+lbm_status lbm_step_launches(const lbm_grid *g, int64_t *blocks_out, int32_t max, int32_t *n);
+
+/* Measurement hook: enqueues launch k (0-based, in lbm_step_launches order) of
+ * one step on its own -- it reads the current populations and writes the
+ * other buffer, which does not become current.  Lets a caller time one
+ * group's kernel in isolation. */
+lbm_status lbm_launch_group(lbm_grid *g, int32_t k, void *stream);
+
+lbm_status lbm_grid_destroy(lbm_grid *g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,69 @@
+// Launch descriptors shared between the C-ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+// Per-face boundary parameters: face id 2*axis + side (side 1 = max face),
+// kinds as lbm_bc, value = wall/inlet velocity or outlet density.
+struct FaceParams {
+  int32_t kind[6];
+  float val[6][3];
+  int32_t periodic;  // bit a set if axis a is periodic
+};
+
+struct StepArgs {
+  const void *src;           // [19][S] populations read (post-collision of the last step)
+  void *dst;                 // [19][S] populations written
+  uint32_t S;                // plane stride in slots
+  const int32_t *nbr;        // [nblocks][18] neighbour block slots (-1 = none)
+  const uint64_t *bbm;       // [nblocks][18] bounce masks
+  const int32_t *coords;     // [nblocks] packed bx | by << 10 | bz << 20
+  int32_t nx, ny, nz;        // box in voxels
+  float omega;               // 1 / tau
+  FaceParams fp;
+};
+
+enum KernelKind : int32_t { kKernelBoundary = 0, kKernelMasked = 1, kKernelFull = 2 };
+
+struct StepLaunch {
+  StepArgs args;
+  int32_t storage;    // lbm_storage
+  int32_t collision;  // 0 BGK, 1 regularized
+  bool lex;           // dense lexicographic single kernel
+  int32_t nlaunch;
+  int32_t kind[4];
+  int32_t first[4];
+  int32_t count[4];
+};
+
+hipError_t launch_step(const StepLaunch &L, hipStream_t s);
+
+// Utility kernels over a slot range [0, nslots) with an optional canonical
+// map (NULL = identity, every slot fluid).
+struct SlotArgs {
+  void *pop_a;               // current buffer
+  void *pop_b;               // other buffer (init writes both)
+  uint32_t S;                // plane stride
+  int64_t nslots;            // slots to visit (multiple of 64 for block layouts)
+  const int32_t *canon;      // [nslots] or NULL
+  int64_t n;                 // canonical length
+  int32_t storage;
+};
+
+hipError_t launch_init_equilibrium(const SlotArgs &A, const double *rho, const double *u,
+                                   hipStream_t s);
+hipError_t launch_read_macroscopic(const SlotArgs &A, void *rho, void *u, int out_f64,
+                                   hipStream_t s);
+hipError_t launch_read_populations(const SlotArgs &A, double *f, hipStream_t s);
+hipError_t launch_write_populations(const SlotArgs &A, const double *f, hipStream_t s);
+// partial sums per 64-slot group (weighted by `weight`) into partial[first_row..]
+hipError_t launch_reduce_partial(const SlotArgs &A, double weight, double *partial,
+                                 hipStream_t s);
+hipError_t launch_reduce_final(const double *partial, int64_t rows, double *out5, hipStream_t s);
+
+}  // namespace lbm

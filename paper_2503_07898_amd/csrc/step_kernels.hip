@@ -1,0 +1,239 @@
+// Fused pull collide-and-stream kernels of liblbm (gfx950).
+//
+// Block layouts: one wave64 per 4^3-voxel block, lane = voxel x+4y+16z,
+// four blocks per 256-thread workgroup.  Populations are structure-of-arrays
+// [19][S] with S = 64 * blocks, so every population load of a wave is one
+// 256-byte (FP32) or 128-byte (16-bit) row of its own block plus the face and
+// edge rows of the neighbour blocks it pulls across.  Neighbour block slots
+// and bounce masks are wave-uniform and come through scalar loads.
+//
+// Kernels per group (the disaggregated design's group-specific operations):
+//   full      -- every pulled source is a fluid voxel; no masks, no checks;
+//   masked    -- non-boundary blocks with obstacles or stationary walls:
+//                halfway bounce-back where the bounce mask says so;
+//   boundary  -- blocks with moving-wall or regularized-face voxels; carries
+//                the per-lane face logic and the regularized reconstruction.
+// The single-kernel comparison arm of block-sparse grids launches the
+// boundary kernel over every block.  The dense comparison arm is the
+// lexicographic kernel at the end of this file.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace lbm {
+
+// Slot of the source of lane `lane` in direction I (pull from x - c_I).
+// Uniform neighbour slots nbv[d-1] for lattice directions d = 1..18; the
+// source block is chosen per lane by which block faces the pull crosses.
+template <int I>
+__device__ __forceinline__ uint32_t pull_slot(int lane, int own, const int32_t (&nbv)[18]) {
+  constexpr int cx = kCx[I], cy = kCy[I], cz = kCz[I];
+  const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+  const bool ox = cx != 0 && lx == (cx > 0 ? 0 : 3);
+  const bool oy = cy != 0 && ly == (cy > 0 ? 0 : 3);
+  const bool oz = cz != 0 && lz == (cz > 0 ? 0 : 3);
+  int b = own;
+  if constexpr (cx != 0) b = ox ? nbv[dir_of(-cx, 0, 0) - 1] : b;
+  if constexpr (cy != 0) b = oy ? nbv[dir_of(0, -cy, 0) - 1] : b;
+  if constexpr (cz != 0) b = oz ? nbv[dir_of(0, 0, -cz) - 1] : b;
+  if constexpr (cx != 0 && cy != 0) b = (ox && oy) ? nbv[dir_of(-cx, -cy, 0) - 1] : b;
+  if constexpr (cx != 0 && cz != 0) b = (ox && oz) ? nbv[dir_of(-cx, 0, -cz) - 1] : b;
+  if constexpr (cy != 0 && cz != 0) b = (oy && oz) ? nbv[dir_of(0, -cy, -cz) - 1] : b;
+  const int local = ((lx - cx) & 3) | (((ly - cy) & 3) << 2) | (((lz - cz) & 3) << 4);
+  return (uint32_t)(b * 64 + local);
+}
+
+template <int COLL>
+__device__ __forceinline__ void collide(float (&h)[Q], float omega) {
+  if constexpr (COLL == kCollRegularized) collide_regularized(h, omega);
+  else collide_bgk(h, omega);
+}
+
+// ------------------------------------------------------ interior kernels --
+template <class ST, int COLL, bool MASKED>
+__global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, int32_t n) {
+  using T = typename ST::T;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  const int lane = threadIdx.x & 63;
+  const T *__restrict__ src = (const T *)a.src;
+  T *__restrict__ dst = (T *)a.dst;
+  const uint32_t S = a.S;
+  const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
+
+  int32_t nbv[18];
+#pragma unroll
+  for (int d = 0; d < 18; ++d) nbv[d] = a.nbr[(size_t)b * 18 + d];
+  uint64_t bm[18];
+  if constexpr (MASKED) {
+#pragma unroll
+    for (int d = 0; d < 18; ++d) bm[d] = a.bbm[(size_t)b * 18 + d];
+  }
+
+  float h[Q];
+  h[0] = ST::load(src, own_slot);
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    uint32_t slot = pull_slot<i>(lane, b, nbv);
+    uint32_t plane = i;
+    if constexpr (MASKED) {
+      if ((bm[i - 1] >> lane) & 1ull) {  // halfway bounce-back
+        slot = own_slot;
+        plane = kOpp[i];
+      }
+    }
+    h[i] = ST::load(src + (size_t)plane * S, slot);
+  });
+
+  collide<COLL>(h, a.omega);
+
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+}
+
+// ------------------------------------------------------ boundary kernel --
+template <class ST, int COLL>
+__global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, int32_t n) {
+  using T = typename ST::T;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  const int lane = threadIdx.x & 63;
+  const T *__restrict__ src = (const T *)a.src;
+  T *__restrict__ dst = (T *)a.dst;
+  const uint32_t S = a.S;
+  const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
+
+  int32_t nbv[18];
+  uint64_t bm[18];
+#pragma unroll
+  for (int d = 0; d < 18; ++d) {
+    nbv[d] = a.nbr[(size_t)b * 18 + d];
+    bm[d] = a.bbm[(size_t)b * 18 + d];
+  }
+  const int packed = a.coords[b];
+  const int gx = (packed & 1023) * 4 + (lane & 3);
+  const int gy = ((packed >> 10) & 1023) * 4 + ((lane >> 2) & 3);
+  const int gz = ((packed >> 20) & 1023) * 4 + (lane >> 4);
+
+  float h[Q];
+  uint32_t unknown = 0;
+  int rface = 0;
+  h[0] = ST::load(src, own_slot);
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const LinkClass lc = classify_link<i>(a.fp, gx, gy, gz, a.nx, a.ny, a.nz);
+    uint32_t slot = pull_slot<i>(lane, b, nbv);
+    uint32_t plane = i;
+    if (lc.kind != kLinkInside || ((bm[i - 1] >> lane) & 1ull)) {
+      slot = own_slot;
+      plane = kOpp[i];
+    }
+    float v = ST::load(src + (size_t)plane * S, slot);
+    if (lc.kind == kLinkMoving) v = v + lc.extra;
+    if (lc.kind == kLinkUnknown) {
+      unknown |= 1u << i;
+      rface = lc.face;
+    }
+    h[i] = v;
+  });
+
+  if (unknown) regularized_face(h, unknown, rface, a.fp, a.omega);
+  else collide<COLL>(h, a.omega);
+
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+}
+
+// ---------------------------------------------- dense lexicographic arm ---
+// One thread per voxel of an all-fluid box stored as [19][nx*ny*nz] with
+// x fastest; face rules evaluated inline for every voxel.
+template <class ST, int COLL>
+__global__ __launch_bounds__(256) void k_lex(StepArgs a) {
+  using T = typename ST::T;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const T *__restrict__ src = (const T *)a.src;
+  T *__restrict__ dst = (T *)a.dst;
+  const uint32_t S = a.S;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const uint32_t own = (uint32_t)x + (uint32_t)nx * ((uint32_t)y + (uint32_t)ny * (uint32_t)z);
+
+  float h[Q];
+  uint32_t unknown = 0;
+  int rface = 0;
+  h[0] = ST::load(src, own);
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const LinkClass lc = classify_link<i>(a.fp, x, y, z, nx, ny, nz);
+    int sx = x - kCx[i], sy = y - kCy[i], sz = z - kCz[i];
+    sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+    sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+    sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+    uint32_t slot = (uint32_t)sx + (uint32_t)nx * ((uint32_t)sy + (uint32_t)ny * (uint32_t)sz);
+    uint32_t plane = i;
+    if (lc.kind != kLinkInside) {
+      slot = own;
+      plane = kOpp[i];
+    }
+    float v = ST::load(src + (size_t)plane * S, slot);
+    if (lc.kind == kLinkMoving) v = v + lc.extra;
+    if (lc.kind == kLinkUnknown) {
+      unknown |= 1u << i;
+      rface = lc.face;
+    }
+    h[i] = v;
+  });
+
+  if (unknown) regularized_face(h, unknown, rface, a.fp, a.omega);
+  else collide<COLL>(h, a.omega);
+
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own, h[i]);
+}
+
+// --------------------------------------------------------------- launch --
+template <class ST, int COLL>
+static hipError_t launch_step_t(const StepLaunch &L, hipStream_t s) {
+  if (L.lex) {
+    dim3 blk(64, 4, 1);
+    dim3 grd((L.args.nx + 63) / 64, (L.args.ny + 3) / 4, L.args.nz);
+    hipLaunchKernelGGL((k_lex<ST, COLL>), grd, blk, 0, s, L.args);
+    return hipGetLastError();
+  }
+  for (int k = 0; k < L.nlaunch; ++k) {
+    const int32_t g0 = L.first[k], n = L.count[k];
+    if (n <= 0) continue;
+    const int nwg = (n + 3) / 4;
+    switch (L.kind[k]) {
+      case kKernelFull:
+        hipLaunchKernelGGL((k_block_interior<ST, COLL, false>), dim3(nwg), dim3(256), 0, s, L.args, g0, n);
+        break;
+      case kKernelMasked:
+        hipLaunchKernelGGL((k_block_interior<ST, COLL, true>), dim3(nwg), dim3(256), 0, s, L.args, g0, n);
+        break;
+      default:
+        hipLaunchKernelGGL((k_block_boundary<ST, COLL>), dim3(nwg), dim3(256), 0, s, L.args, g0, n);
+        break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_step(const StepLaunch &L, hipStream_t s) {
+  const bool reg = L.collision == kCollRegularized;
+  switch (L.storage) {
+    case LBM_F32: return reg ? launch_step_t<StoreF32, kCollRegularized>(L, s) : launch_step_t<StoreF32, kCollBGK>(L, s);
+    case LBM_F16_SHIFTED: return reg ? launch_step_t<StoreF16, kCollRegularized>(L, s) : launch_step_t<StoreF16, kCollBGK>(L, s);
+    case LBM_BF16_SHIFTED: return reg ? launch_step_t<StoreBF16, kCollRegularized>(L, s) : launch_step_t<StoreBF16, kCollBGK>(L, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -1,0 +1,192 @@
+// Off-hot-path kernels of liblbm: equilibrium initialisation, macroscopic
+// read-out, population checkpoint read/write and FP64 reductions.  All of
+// them visit slots in storage order and exchange data in canonical order
+// through the slot -> canonical index map.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace lbm {
+
+__device__ __forceinline__ int64_t canon_of(const SlotArgs &A, int64_t slot) {
+  return A.canon ? (int64_t)A.canon[slot] : slot;
+}
+
+// FP64 equilibrium, shifted: f^eq_i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
+template <class ST>
+__global__ void k_init_eq(SlotArgs A, const double *rho, const double *u) {
+  using T = typename ST::T;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= A.nslots) return;
+  const int64_t c = canon_of(A, slot);
+  T *pa = (T *)A.pop_a, *pb = (T *)A.pop_b;
+  if (c < 0) {
+    for (int i = 0; i < Q; ++i) {
+      pa[(size_t)i * A.S + slot] = ST::from_double(0.0);
+      pb[(size_t)i * A.S + slot] = ST::from_double(0.0);
+    }
+    return;
+  }
+  const double r = rho[c], ux = u[c], uy = u[A.n + c], uz = u[2 * A.n + c];
+  const double uu = ux * ux + uy * uy + uz * uz;
+  for (int i = 0; i < Q; ++i) {
+    const double cu = kCx[i] * ux + kCy[i] * uy + kCz[i] * uz;
+    const double h = weight_d(i) * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    const T v = ST::from_double(h);
+    pa[(size_t)i * A.S + slot] = v;
+    pb[(size_t)i * A.S + slot] = v;
+  }
+}
+
+template <class ST>
+__global__ void k_read_macro(SlotArgs A, void *rho_out, void *u_out, int f64) {
+  using T = typename ST::T;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= A.nslots) return;
+  const int64_t c = canon_of(A, slot);
+  if (c < 0) return;
+  const T *p = (const T *)A.pop_a;
+  double d = 0, jx = 0, jy = 0, jz = 0;
+  for (int i = 0; i < Q; ++i) {
+    const double h = ST::to_double(p[(size_t)i * A.S + slot]);
+    d += h;
+    jx += kCx[i] * h;
+    jy += kCy[i] * h;
+    jz += kCz[i] * h;
+  }
+  const double r = 1.0 + d;
+  if (f64) {
+    double *ro = (double *)rho_out, *uo = (double *)u_out;
+    ro[c] = r;
+    uo[c] = jx / r;
+    uo[A.n + c] = jy / r;
+    uo[2 * A.n + c] = jz / r;
+  } else {
+    float *ro = (float *)rho_out, *uo = (float *)u_out;
+    ro[c] = (float)r;
+    uo[c] = (float)(jx / r);
+    uo[A.n + c] = (float)(jy / r);
+    uo[2 * A.n + c] = (float)(jz / r);
+  }
+}
+
+template <class ST>
+__global__ void k_read_pop(SlotArgs A, double *f) {
+  using T = typename ST::T;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= A.nslots) return;
+  const int64_t c = canon_of(A, slot);
+  if (c < 0) return;
+  const T *p = (const T *)A.pop_a;
+  for (int i = 0; i < Q; ++i) f[(size_t)i * A.n + c] = weight_d(i) + ST::to_double(p[(size_t)i * A.S + slot]);
+}
+
+template <class ST>
+__global__ void k_write_pop(SlotArgs A, const double *f) {
+  using T = typename ST::T;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= A.nslots) return;
+  const int64_t c = canon_of(A, slot);
+  if (c < 0) return;
+  T *p = (T *)A.pop_a;
+  for (int i = 0; i < Q; ++i) p[(size_t)i * A.S + slot] = ST::from_double(f[(size_t)i * A.n + c] - weight_d(i));
+}
+
+// Per 64-slot row partial sums: mass, momentum, kinetic energy, times weight.
+// One wave per row, butterfly reduction in a fixed order.
+template <class ST>
+__global__ __launch_bounds__(64) void k_reduce_partial(SlotArgs A, double weight, double *partial) {
+  using T = typename ST::T;
+  const int64_t row = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t slot = row * 64 + lane;
+  double v[5] = {0, 0, 0, 0, 0};
+  if (slot < A.nslots && canon_of(A, slot) >= 0) {
+    const T *p = (const T *)A.pop_a;
+    double d = 0, jx = 0, jy = 0, jz = 0;
+    for (int i = 0; i < Q; ++i) {
+      const double h = ST::to_double(p[(size_t)i * A.S + slot]);
+      d += h;
+      jx += kCx[i] * h;
+      jy += kCy[i] * h;
+      jz += kCz[i] * h;
+    }
+    const double r = 1.0 + d;
+    v[0] = r;
+    v[1] = jx;
+    v[2] = jy;
+    v[3] = jz;
+    v[4] = 0.5 * (jx * jx + jy * jy + jz * jz) / r;
+  }
+  for (int k = 0; k < 5; ++k) {
+    double x = v[k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[k] = x;
+  }
+  if (lane == 0)
+    for (int k = 0; k < 5; ++k) partial[row * 5 + k] = weight * v[k];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double *partial, int64_t rows, double *out5) {
+  __shared__ double sh[5][256];
+  const int t = threadIdx.x;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t r = t; r < rows; r += 256)
+    for (int k = 0; k < 5; ++k) acc[k] += partial[r * 5 + k];
+  for (int k = 0; k < 5; ++k) sh[k][t] = acc[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int k = 0; k < 5; ++k) sh[k][t] += sh[k][t + w];
+    __syncthreads();
+  }
+  if (t < 5) out5[t] = sh[t][0];
+}
+
+template <template <class> class K, class... Args>
+static hipError_t dispatch(int storage, dim3 g, dim3 b, hipStream_t s, Args... args) {
+  switch (storage) {
+    case LBM_F32: hipLaunchKernelGGL(K<StoreF32>::fn, g, b, 0, s, args...); break;
+    case LBM_F16_SHIFTED: hipLaunchKernelGGL(K<StoreF16>::fn, g, b, 0, s, args...); break;
+    case LBM_BF16_SHIFTED: hipLaunchKernelGGL(K<StoreBF16>::fn, g, b, 0, s, args...); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class ST> struct InitK { static constexpr auto fn = k_init_eq<ST>; };
+template <class ST> struct MacroK { static constexpr auto fn = k_read_macro<ST>; };
+template <class ST> struct RPopK { static constexpr auto fn = k_read_pop<ST>; };
+template <class ST> struct WPopK { static constexpr auto fn = k_write_pop<ST>; };
+template <class ST> struct RedK { static constexpr auto fn = k_reduce_partial<ST>; };
+
+static dim3 grid_for(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_init_equilibrium(const SlotArgs &A, const double *rho, const double *u, hipStream_t s) {
+  if (A.nslots == 0) return hipSuccess;
+  return dispatch<InitK>(A.storage, grid_for(A.nslots), dim3(256), s, A, rho, u);
+}
+hipError_t launch_read_macroscopic(const SlotArgs &A, void *rho, void *u, int out_f64, hipStream_t s) {
+  if (A.nslots == 0) return hipSuccess;
+  return dispatch<MacroK>(A.storage, grid_for(A.nslots), dim3(256), s, A, rho, u, out_f64);
+}
+hipError_t launch_read_populations(const SlotArgs &A, double *f, hipStream_t s) {
+  if (A.nslots == 0) return hipSuccess;
+  return dispatch<RPopK>(A.storage, grid_for(A.nslots), dim3(256), s, A, f);
+}
+hipError_t launch_write_populations(const SlotArgs &A, const double *f, hipStream_t s) {
+  if (A.nslots == 0) return hipSuccess;
+  return dispatch<WPopK>(A.storage, grid_for(A.nslots), dim3(256), s, A, f);
+}
+hipError_t launch_reduce_partial(const SlotArgs &A, double weight, double *partial, hipStream_t s) {
+  const int64_t rows = (A.nslots + 63) / 64;
+  if (rows == 0) return hipSuccess;
+  return dispatch<RedK>(A.storage, dim3((unsigned)rows), dim3(64), s, A, weight, partial);
+}
+hipError_t launch_reduce_final(const double *partial, int64_t rows, double *out5, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partial, rows, out5);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,286 @@
+"""ctypes binding of liblbm.so (include/lbm.h).
+
+Argument marshalling only: every step of the path runs in liblbm's HIP
+kernels.  PyTorch supplies device memory (the workspace and the caller's
+arrays) and the stream.  There is no fallback: if the library is not built,
+loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+# enums of include/lbm.h
+LBM_OK = 0
+DENSE, BLOCK_SPARSE, MULTIRES = 0, 1, 2
+F32, F16_SHIFTED, BF16_SHIFTED = 0, 1, 2
+BGK, REGULARIZED, MLP = 0, 1, 2
+PLAIN_SINGLE_KERNEL, DISAGG = 0, 1
+XMIN, XMAX, YMIN, YMAX, ZMIN, ZMAX = range(6)
+BC_BOUNCE_BACK, BC_MOVING_WALL, BC_REG_VELOCITY, BC_REG_PRESSURE = range(4)
+MAP_GROUPS, MAP_COORDS, MAP_NEIGHBOURS, MAP_FLUIDMASK, MAP_CANONICAL = range(5)
+
+STORAGE_BYTES = {F32: 4, F16_SHIFTED: 2, BF16_SHIFTED: 2}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"liblbm status {status}: {msg}")
+        self.status = status
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("periodic", ctypes.c_uint8 * 3),
+        ("num_levels", ctypes.c_int32),
+        ("fluid_mask", ctypes.c_void_p),
+        ("level_map", ctypes.c_void_p),
+        ("tau", ctypes.c_double),
+        ("storage", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2503_07898_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        sigs = {
+            "lbm_last_error": ([], ctypes.c_char_p),
+            "lbm_grid_create": ([ctypes.POINTER(GridDesc), ctypes.POINTER(vp)], i32),
+            "lbm_set_boundary": ([vp, i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
+            "lbm_grid_commit": ([vp, ctypes.POINTER(sz)], i32),
+            "lbm_grid_bind": ([vp, vp, sz, vp], i32),
+            "lbm_num_voxels": ([vp, i32, ctypes.POINTER(i64)], i32),
+            "lbm_init_equilibrium": ([vp, i32, vp, vp, vp], i32),
+            "lbm_step": ([vp, i32, vp], i32),
+            "lbm_read_macroscopic": ([vp, i32, vp, vp, i32, vp], i32),
+            "lbm_reduce": ([vp, vp, vp], i32),
+            "lbm_read_populations": ([vp, i32, vp, vp], i32),
+            "lbm_write_populations": ([vp, i32, vp, vp], i32),
+            "lbm_get_index_map": ([vp, i32, i32, vp, ctypes.POINTER(sz)], i32),
+            "lbm_step_launches": ([vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)], i32),
+            "lbm_launch_group": ([vp, i32, vp], i32),
+            "lbm_grid_destroy": ([vp], i32),
+        }
+        for name, (args, res) in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != LBM_OK:
+        raise LbmError(status, lib().lbm_last_error().decode())
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+# ------------------------------------------------------ thin C-ABI wrappers --
+# Same names as the C functions; each marshals its arguments and checks the
+# returned status.
+
+def lbm_grid_create(desc: GridDesc) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(lib().lbm_grid_create(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def lbm_set_boundary(g, face: int, kind: int, value=(0.0, 0.0, 0.0)) -> None:
+    v = (ctypes.c_double * 3)(*[float(x) for x in value])
+    check(lib().lbm_set_boundary(g, int(face), int(kind), v))
+
+
+def lbm_grid_commit(g) -> int:
+    n = ctypes.c_size_t()
+    check(lib().lbm_grid_commit(g, ctypes.byref(n)))
+    return n.value
+
+
+def lbm_grid_bind(g, ptr: int, nbytes: int, stream=None) -> None:
+    check(lib().lbm_grid_bind(g, ctypes.c_void_p(ptr), nbytes, _stream_ptr(stream)))
+
+
+def lbm_num_voxels(g, level: int = 0) -> int:
+    n = ctypes.c_int64()
+    check(lib().lbm_num_voxels(g, level, ctypes.byref(n)))
+    return n.value
+
+
+def lbm_init_equilibrium(g, level: int, rho_ptr: int, u_ptr: int, stream=None) -> None:
+    check(lib().lbm_init_equilibrium(g, level, rho_ptr, u_ptr, _stream_ptr(stream)))
+
+
+def lbm_step(g, n: int, stream=None) -> None:
+    check(lib().lbm_step(g, int(n), _stream_ptr(stream)))
+
+
+def lbm_read_macroscopic(g, level: int, rho_ptr: int, u_ptr: int, f64: bool, stream=None) -> None:
+    check(lib().lbm_read_macroscopic(g, level, rho_ptr, u_ptr, 1 if f64 else 0, _stream_ptr(stream)))
+
+
+def lbm_reduce(g, out_ptr: int, stream=None) -> None:
+    check(lib().lbm_reduce(g, out_ptr, _stream_ptr(stream)))
+
+
+def lbm_read_populations(g, level: int, f_ptr: int, stream=None) -> None:
+    check(lib().lbm_read_populations(g, level, f_ptr, _stream_ptr(stream)))
+
+
+def lbm_write_populations(g, level: int, f_ptr: int, stream=None) -> None:
+    check(lib().lbm_write_populations(g, level, f_ptr, _stream_ptr(stream)))
+
+
+def lbm_get_index_map(g, level: int, which: int) -> np.ndarray:
+    n = ctypes.c_size_t()
+    check(lib().lbm_get_index_map(g, level, which, None, ctypes.byref(n)))
+    dtype = {MAP_GROUPS: np.int64, MAP_COORDS: np.int32, MAP_NEIGHBOURS: np.int32,
+             MAP_FLUIDMASK: np.uint64, MAP_CANONICAL: np.int64}[which]
+    out = np.zeros(n.value, dtype)
+    check(lib().lbm_get_index_map(g, level, which, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+    return out
+
+
+def lbm_step_launches(g) -> list[int]:
+    n = ctypes.c_int32()
+    buf = (ctypes.c_int64 * 8)()
+    check(lib().lbm_step_launches(g, buf, 8, ctypes.byref(n)))
+    return [int(buf[k]) for k in range(n.value)]
+
+
+def lbm_launch_group(g, k: int, stream=None) -> None:
+    check(lib().lbm_launch_group(g, int(k), _stream_ptr(stream)))
+
+
+def lbm_grid_destroy(g) -> None:
+    check(lib().lbm_grid_destroy(g))
+
+
+# ------------------------------------------------------------ convenience --
+
+@dataclass
+class Grid:
+    """One liblbm grid with its device workspace held as a torch tensor.
+
+    fluid: uint8 (nz, ny, nx) or None; faces: {face: (kind, value3)}.
+    """
+    nx: int
+    ny: int
+    nz: int
+    kind: int = DENSE
+    periodic: tuple = (True, True, True)
+    fluid: np.ndarray | None = None
+    tau: float = 0.6
+    storage: int = F32
+    collision: int = BGK
+    schedule: int = DISAGG
+    faces: dict = field(default_factory=dict)
+    device: str = "cuda"
+
+    def __post_init__(self):
+        d = GridDesc()
+        d.kind = self.kind
+        d.nx, d.ny, d.nz = self.nx, self.ny, self.nz
+        for a in range(3):
+            d.periodic[a] = 1 if self.periodic[a] else 0
+        d.num_levels = 1
+        self._mask = None
+        if self.fluid is not None:
+            self._mask = np.ascontiguousarray(self.fluid, np.uint8)
+            assert self._mask.shape == (self.nz, self.ny, self.nx)
+            d.fluid_mask = self._mask.ctypes.data
+        d.tau = float(self.tau)
+        d.storage, d.collision, d.schedule = self.storage, self.collision, self.schedule
+        self.h = lbm_grid_create(d)
+        for face, (k, val) in self.faces.items():
+            lbm_set_boundary(self.h, face, k, val)
+        self.workspace_bytes = lbm_grid_commit(self.h)
+        self.ws = None
+
+    def bind(self):
+        import torch
+        self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        lbm_grid_bind(self.h, self.ws.data_ptr(), self.workspace_bytes)
+        return self
+
+    @property
+    def n(self) -> int:
+        return lbm_num_voxels(self.h, 0)
+
+    def init_equilibrium(self, rho, u):
+        """rho [N], u [3][N] canonical order (numpy or torch, converted to FP64 on device)."""
+        import torch
+        r = torch.as_tensor(np.asarray(rho, np.float64).reshape(-1)).to(self.device)
+        v = torch.as_tensor(np.asarray(u, np.float64).reshape(3, -1)).contiguous().to(self.device)
+        assert r.numel() == self.n and v.shape[1] == self.n
+        lbm_init_equilibrium(self.h, 0, r.data_ptr(), v.data_ptr())
+        torch.cuda.current_stream().synchronize()
+
+    def step(self, n: int = 1):
+        lbm_step(self.h, n)
+
+    def macroscopic(self, f64: bool = True):
+        import torch
+        dt = torch.float64 if f64 else torch.float32
+        rho = torch.empty(self.n, dtype=dt, device=self.device)
+        u = torch.empty(3, self.n, dtype=dt, device=self.device)
+        lbm_read_macroscopic(self.h, 0, rho.data_ptr(), u.data_ptr(), f64)
+        return rho, u
+
+    def populations(self):
+        import torch
+        f = torch.empty(19, self.n, dtype=torch.float64, device=self.device)
+        lbm_read_populations(self.h, 0, f.data_ptr())
+        return f
+
+    def write_populations(self, f):
+        import torch
+        t = torch.as_tensor(f, dtype=torch.float64).reshape(19, self.n).contiguous().to(self.device)
+        lbm_write_populations(self.h, 0, t.data_ptr())
+        torch.cuda.current_stream().synchronize()
+
+    def reduce(self):
+        import torch
+        out = torch.empty(5, dtype=torch.float64, device=self.device)
+        lbm_reduce(self.h, out.data_ptr())
+        return out
+
+    def index_map(self, which: int) -> np.ndarray:
+        return lbm_get_index_map(self.h, 0, which)
+
+    def launches(self) -> list[int]:
+        return lbm_step_launches(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lbm_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

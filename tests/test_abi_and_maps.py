@@ -1,0 +1,169 @@
+"""CPU tests of the C ABI and of the host grid builder (no GPU needed).
+
+* liblbm.so loads and exports every function include/lbm.h declares;
+* argument and call-order errors come back as status codes with messages;
+* the library's index maps equal the oracle's reference builder bit for bit
+  on randomized masks (and the reference builder's neighbour table equals an
+  O(n^2) brute-force scan);
+* the launch structure matches table dissBlock: the naive arm is one kernel
+  over n_b + n_nb blocks, memory grouping launches one kernel per group over
+  exactly that group's blocks.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_07898_amd import lbm, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.lib()
+    names = _declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _desc(**kw):
+    d = lbm.GridDesc()
+    d.kind = kw.get("kind", lbm.DENSE)
+    d.nx, d.ny, d.nz = kw.get("n", (8, 8, 8))
+    for a in range(3):
+        d.periodic[a] = kw.get("periodic", (1, 1, 1))[a]
+    d.num_levels = kw.get("levels", 1)
+    d.tau = kw.get("tau", 0.6)
+    d.storage = kw.get("storage", lbm.F32)
+    d.collision = kw.get("collision", lbm.BGK)
+    d.schedule = kw.get("schedule", lbm.DISAGG)
+    return d
+
+
+def test_error_paths():
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_grid_create(_desc(tau=0.5))
+    assert e.value.status == -1 and "tau" in str(e.value)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_grid_create(_desc(n=(10, 8, 8)))  # block layout needs multiples of 4
+    g = lbm.lbm_grid_create(_desc(periodic=(0, 1, 1)))
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_boundary(g, lbm.YMIN, lbm.BC_BOUNCE_BACK)  # periodic axis
+    assert "periodic" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_step(g, 1, stream=0)  # before commit/bind/init
+    assert e.value.status == -4
+    lbm.lbm_grid_commit(g)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_boundary(g, lbm.XMIN, lbm.BC_BOUNCE_BACK)  # after commit
+    assert e.value.status == -4
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_grid_bind(g, 0x1000 + 7, 1 << 30, stream=0)  # misaligned workspace
+    assert "aligned" in str(e.value)
+    lbm.lbm_grid_destroy(g)
+    # a voxel on two regularized faces is rejected at commit
+    g = lbm.lbm_grid_create(_desc(periodic=(0, 0, 1)))
+    lbm.lbm_set_boundary(g, lbm.XMIN, lbm.BC_REG_VELOCITY, (0.05, 0, 0))
+    lbm.lbm_set_boundary(g, lbm.YMIN, lbm.BC_REG_PRESSURE, (1, 0, 0))
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_grid_commit(g)
+    assert "two regularized" in str(e.value)
+    lbm.lbm_grid_destroy(g)
+    # dense grids must be all fluid
+    fl = np.ones((8, 8, 8), np.uint8)
+    fl[3, 3, 3] = 0
+    d = _desc()
+    d.fluid_mask = fl.ctypes.data
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_grid_create(d)
+
+
+CASES = [
+    # (n, periodic, face kinds for XMIN..ZMAX, dense)
+    ((16, 12, 8), (False, True, True), ("vel", "pres", "bb", "bb", "bb", "bb"), False),
+    ((12, 16, 12), (False, False, False), ("vel", "pres", "bb", "bb", "bb", "bb"), False),
+    ((16, 16, 16), (True, True, True), ("bb",) * 6, False),
+    ((12, 12, 16), (True, False, False), ("bb", "bb", "bb", "moving", "bb", "bb"), False),
+    ((16, 8, 12), (False, False, False), ("bb", "bb", "bb", "bb", "bb", "moving"), True),
+    ((8, 12, 16), (True, False, True), ("bb",) * 6, True),
+]
+KIND = {"bb": lbm.BC_BOUNCE_BACK, "moving": lbm.BC_MOVING_WALL,
+        "vel": lbm.BC_REG_VELOCITY, "pres": lbm.BC_REG_PRESSURE}
+
+
+def _faces(periodic, kinds):
+    val = {"bb": (0, 0, 0), "moving": (0.1, 0, 0), "vel": (0.05, 0, 0), "pres": (1.0, 0, 0)}
+    return {f: (KIND[kinds[f]], val[kinds[f]]) for f in range(6) if not periodic[f // 2]}
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_index_maps_bit_exact(orc, case, seed):
+    n, periodic, kinds, dense = CASES[case]
+    if dense:
+        fluid = None
+    else:
+        fluid = workloads.random_mask(*n, seed=seed + 10 * case, solid_fraction=0.15,
+                                      empty_block_fraction=0.25)
+        if seed == 3:  # some blocks all fluid with full neighbourhoods
+            fluid[:, :, :] = 1
+            fluid[:4, :4, :4] = 0
+    g = lbm.Grid(*n, kind=lbm.DENSE if dense else lbm.BLOCK_SPARSE, periodic=periodic,
+                 fluid=fluid, faces=_faces(periodic, kinds), device="cpu")
+    okinds = [{"bb": orc.BB, "moving": orc.MOVING, "vel": orc.REG_VEL, "pres": orc.REG_PRES}[k]
+              for k in kinds]
+    ref = orc.build_block_maps(*n, periodic, fluid, okinds, dense)
+    groups = g.index_map(lbm.MAP_GROUPS)
+    assert tuple(groups[:3]) == ref["groups"]
+    nb = int(groups[3])
+    assert np.array_equal(g.index_map(lbm.MAP_COORDS).reshape(nb, 3), ref["coords"])
+    assert np.array_equal(g.index_map(lbm.MAP_NEIGHBOURS).reshape(nb, 18), ref["nbr"])
+    assert np.array_equal(g.index_map(lbm.MAP_FLUIDMASK), ref["fmask"])
+    assert np.array_equal(g.index_map(lbm.MAP_CANONICAL), ref["canon"])
+    assert g.n == ref["n_fluid"]
+    g.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_reference_builder_neighbours_brute_force(orc, seed):
+    n = (12, 8, 16)
+    periodic = (seed % 2 == 0, True, seed % 3 == 0)
+    fluid = workloads.random_mask(*n, seed=100 + seed, empty_block_fraction=0.3)
+    ref = orc.build_block_maps(*n, periodic, fluid, [orc.BB] * 6, False)
+    bf = orc.brute_force_neighbours(ref["coords"], periodic, (n[0] // 4, n[1] // 4, n[2] // 4))
+    assert np.array_equal(bf, ref["nbr"])
+    # Morton order within each group, boundary group first
+    keys = [orc.morton_key(*c) for c in ref["coords"]]
+    a, b, _ = ref["groups"]
+    for lo, hi in ((0, a), (a, a + b), (a + b, len(keys))):
+        assert keys[lo:hi] == sorted(keys[lo:hi])
+
+
+def test_launch_structure_table_dissBlock():
+    n = (32, 16, 16)
+    fluid, _ = workloads.sphere_packing(*n, seed=5, rmin=2, rmax=5, target_active=0.7)
+    faces = {lbm.XMIN: (lbm.BC_REG_VELOCITY, (0.05, 0, 0)), lbm.XMAX: (lbm.BC_REG_PRESSURE, (1, 0, 0)),
+             lbm.YMIN: (lbm.BC_BOUNCE_BACK, (0, 0, 0)), lbm.YMAX: (lbm.BC_BOUNCE_BACK, (0, 0, 0)),
+             lbm.ZMIN: (lbm.BC_BOUNCE_BACK, (0, 0, 0)), lbm.ZMAX: (lbm.BC_BOUNCE_BACK, (0, 0, 0))}
+    common = dict(kind=lbm.BLOCK_SPARSE, periodic=(False, False, False), fluid=fluid, faces=faces,
+                  device="cpu")
+    naive = lbm.Grid(*n, schedule=lbm.PLAIN_SINGLE_KERNEL, **common)
+    disagg = lbm.Grid(*n, schedule=lbm.DISAGG, **common)
+    gb, gm, gf, total = disagg.index_map(lbm.MAP_GROUPS)
+    assert naive.launches() == [total]
+    assert sorted(disagg.launches()) == sorted(x for x in (gb, gm, gf) if x > 0)
+    assert gb == 2 * (n[1] // 4) * (n[2] // 4)  # inlet and outlet block layers
+    # memory grouping needs no boundary metadata: the two arms have the same workspace
+    assert naive.workspace_bytes == disagg.workspace_bytes
