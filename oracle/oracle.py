@@ -25,6 +25,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "lbm_oracle.c")
+SRC_MR_PATH = os.path.join(HERE, "lbm_oracle_multires.c")
 Q = 19
 
 # face ids and boundary kinds of the oracle (its own numbering)
@@ -36,12 +37,12 @@ BGK, REGULARIZED = 0, 1
 def build(force: bool = False) -> str:
     """Compile lbm_oracle.c with gcc (-O3 -fopenmp) into liboracle.so."""
     if force or not os.path.exists(LIB_PATH) or (
-        os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH)
+        os.path.getmtime(LIB_PATH) < max(os.path.getmtime(SRC_PATH), os.path.getmtime(SRC_MR_PATH))
     ):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(
             ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-             "-Wall", "-Wextra", "-o", tmp, SRC_PATH, "-lm"]
+             "-Wall", "-Wextra", "-o", tmp, SRC_PATH, SRC_MR_PATH, "-lm"]
         )
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -55,6 +56,20 @@ class _Grid(ctypes.Structure):
         ("bc_kind", ctypes.c_int32 * 6),
         ("bc_val", (ctypes.c_double * 3) * 6),
         ("tau", ctypes.c_double),
+        ("collision", ctypes.c_int32),
+    ]
+
+
+class _MrGrid(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
+        ("periodic", ctypes.c_int32 * 3),
+        ("level_map", ctypes.POINTER(ctypes.c_uint8)),
+        ("fluid", ctypes.POINTER(ctypes.c_uint8)),
+        ("bc_kind", ctypes.c_int32 * 6),
+        ("bc_val", (ctypes.c_double * 3) * 6),
+        ("tau_coarsest", ctypes.c_double),
         ("collision", ctypes.c_int32),
     ]
 
@@ -88,6 +103,11 @@ def lib():
         L.orc_collide_regularized.restype = None
         L.orc_f1.argtypes = [dp, dp, dp]
         L.orc_f1.restype = None
+        pp = ctypes.POINTER(ctypes.POINTER(ctypes.c_double))
+        L.orc_mr_run.argtypes = [ctypes.POINTER(_MrGrid), pp, pp, pp, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int32)]
+        L.orc_mr_mass.argtypes = [ctypes.POINTER(_MrGrid), pp]
+        L.orc_mr_mass.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -395,3 +415,95 @@ def brute_force_neighbours(coords, periodic, nblocks_axis):
                 if list(coords[t]) == want:
                     out[s, d - 1] = t
     return out
+
+
+# ------------------------------------------------------------- multires ----
+
+@dataclass
+class MultiresGrid:
+    """Multi-resolution box for the oracle (lbm_oracle_multires.c).
+
+    level_map: uint8 (nz, ny, nx) at the finest resolution, 0 = finest;
+    fluid: uint8 (nz, ny, nx) or None (solids only at level 0).
+    Per-level state arrays are shaped (nz >> l, ny >> l, nx >> l, 19).
+    """
+    nx: int
+    ny: int
+    nz: int
+    levels: int
+    level_map: np.ndarray
+    periodic: tuple = (True, True, True)
+    fluid: np.ndarray | None = None
+    bc: list = field(default_factory=lambda: [(BB, (0.0, 0.0, 0.0))] * 6)
+    tau_coarsest: float = 0.6
+    collision: int = BGK
+
+    def _struct(self):
+        g = _MrGrid()
+        g.nx, g.ny, g.nz, g.levels = self.nx, self.ny, self.nz, self.levels
+        for a in range(3):
+            g.periodic[a] = 1 if self.periodic[a] else 0
+        self._lm = np.ascontiguousarray(self.level_map, np.uint8)
+        assert self._lm.shape == (self.nz, self.ny, self.nx)
+        g.level_map = self._lm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        if self.fluid is not None:
+            self._fl = np.ascontiguousarray(self.fluid, np.uint8)
+            g.fluid = self._fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        else:
+            g.fluid = ctypes.POINTER(ctypes.c_uint8)()
+        for k in range(6):
+            kind, val = self.bc[k]
+            g.bc_kind[k] = int(kind)
+            for a in range(3):
+                g.bc_val[k][a] = float(val[a]) if a < len(val) else 0.0
+        g.tau_coarsest = float(self.tau_coarsest)
+        g.collision = int(self.collision)
+        return g
+
+    def shape(self, l):
+        return (self.nz >> l, self.ny >> l, self.nx >> l)
+
+    def active(self, l):
+        """bool (nz>>l, ny>>l, nx>>l): cells that are fluid voxels of level l."""
+        s = 1 << l
+        a = self.level_map[::s, ::s, ::s] == l
+        if l == 0 and self.fluid is not None:
+            a = a & (np.asarray(self.fluid) != 0)
+        return a
+
+    def tau(self, l):
+        return 0.5 + (self.tau_coarsest - 0.5) * 2 ** (self.levels - 1 - l)
+
+    def init_equilibrium(self, rho, u):
+        """rho[l] (shape(l)), u[l] (shape(l)+(3,)) -> list of f[l]."""
+        out = []
+        for l in range(self.levels):
+            nz, ny, nx = self.shape(l)
+            g = Grid(nx, ny, nz)
+            out.append(g.init_equilibrium(rho[l], u[l]))
+        return out
+
+    def run(self, f, nsteps):
+        L = self.levels
+        bufs = [[np.array(f[l], np.float64, order="C", copy=True) for l in range(L)] for _ in range(3)]
+        ptrs = [(ctypes.POINTER(ctypes.c_double) * L)(*[_dp(b[l]) for l in range(L)]) for b in bufs]
+        which = (ctypes.c_int32 * L)()
+        g = self._struct()
+        r = lib().orc_mr_run(ctypes.byref(g), ptrs[0], ptrs[1], ptrs[2], int(nsteps), which)
+        if r != 0:
+            raise ValueError(f"oracle multires run failed ({r})")
+        return [bufs[which[l]][l] for l in range(L)]
+
+    def mass(self, f):
+        L = self.levels
+        arrs = [np.ascontiguousarray(f[l], np.float64) for l in range(L)]
+        ptr = (ctypes.POINTER(ctypes.c_double) * L)(*[_dp(a) for a in arrs])
+        g = self._struct()
+        return lib().orc_mr_mass(ctypes.byref(g), ptr)
+
+    def macroscopic(self, f):
+        out = []
+        for l in range(self.levels):
+            nz, ny, nx = self.shape(l)
+            out.append(Grid(nx, ny, nz).macroscopic(np.ascontiguousarray(f[l])))
+        return out

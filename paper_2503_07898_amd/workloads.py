@@ -120,3 +120,101 @@ def random_mask(nx: int, ny: int, nz: int, seed: int, solid_fraction: float = 0.
     e = np.repeat(np.repeat(np.repeat(empty, block, 0), block, 1), block, 2)
     fluid[e] = 0
     return fluid
+
+
+# ------------------------------------------------------ multi-resolution ---
+
+def refine_level_map(nx: int, ny: int, nz: int, levels: int, desired: np.ndarray,
+                     periodic=(True, True, True)) -> np.ndarray:
+    """Block-aligned, 2:1-balanced level map (uint8 (nz, ny, nx), 0 = finest).
+
+    desired: int array (nz/4, ny/4, nx/4), the coarsest level allowed for each
+    finest-level block of 4^3 voxels.  A level-l block covers 2^l finest
+    blocks per axis.  Starting from the coarsest level, every block whose
+    region asks for a finer level is split into 8; then blocks are split
+    until every two blocks that share a face, edge or corner differ by at
+    most one level.
+    """
+    L = levels
+    top = 4 << (L - 1)
+    assert nx % top == 0 and ny % top == 0 and nz % top == 0, "box must hold whole coarsest blocks"
+    shp = (nz // 4, ny // 4, nx // 4)
+    des = np.asarray(desired).reshape(shp)
+    lv = np.full(shp, L - 1, np.int16)
+
+    def region_reduce(a, s, fn):
+        r = a.reshape(shp[0] // s, s, shp[1] // s, s, shp[2] // s, s)
+        return fn(fn(fn(r, axis=5), axis=3), axis=1)
+
+    def expand(a, s):
+        return np.repeat(np.repeat(np.repeat(a, s, 0), s, 1), s, 2)
+
+    for l in range(L - 1, 0, -1):
+        s = 1 << l
+        at_l = region_reduce(lv == l, s, np.all)
+        need = region_reduce(des, s, np.min) < l
+        lv[expand(at_l & need, s)] = l - 1
+
+    def neighbour_min(a):
+        # 26-neighbourhood minimum; periodic axes wrap, others repeat the edge
+        m = a.copy()
+        pad = np.pad(a, 1, mode="wrap")
+        for ax in range(3):
+            if not periodic[2 - ax]:
+                sl = [slice(None)] * 3
+                src = [slice(None)] * 3
+                sl[ax], src[ax] = slice(0, 1), slice(1, 2)
+                pad[tuple(sl)] = pad[tuple(src)]
+                sl[ax], src[ax] = slice(-1, None), slice(-2, -1)
+                pad[tuple(sl)] = pad[tuple(src)]
+        for dz in range(3):
+            for dy in range(3):
+                for dx in range(3):
+                    m = np.minimum(m, pad[dz:dz + shp[0], dy:dy + shp[1], dx:dx + shp[2]])
+        return m
+
+    while True:
+        nm = neighbour_min(lv)
+        bad = lv - nm >= 2
+        if not bad.any():
+            break
+        for l in range(L - 1, 1, -1):
+            s = 1 << l
+            reg = region_reduce(bad & (lv == l), s, np.any)
+            lv[expand(reg, s) & (lv == l)] = l - 1
+    return expand(lv.astype(np.uint8), 4)
+
+
+def multires_sphere(nx: int = 512, ny: int = 256, nz: int = 256, levels: int = 3,
+                    center=(128.0, 128.0, 128.0), radius: float = 16.0, bands=(24.0, 48.0),
+                    periodic=(False, True, True)):
+    """Flow past a sphere on a multi-resolution grid (finest resolution box).
+
+    Finest level (0) on every block within bands[0] finest cells of the
+    sphere surface, level 1 within a further bands[1] cells, coarser beyond.
+    Returns (level_map uint8 (nz,ny,nx), fluid uint8 (nz,ny,nx)); the solid
+    sphere is the set of voxel positions (integer coordinates) with
+    |p - center| <= radius.
+    """
+    bz, by, bx = nz // 4, ny // 4, nx // 4
+    zc, yc, xc = np.meshgrid(np.arange(bz) * 4 + 1.5, np.arange(by) * 4 + 1.5,
+                             np.arange(bx) * 4 + 1.5, indexing="ij")
+    d = np.sqrt((xc - center[0]) ** 2 + (yc - center[1]) ** 2 + (zc - center[2]) ** 2)
+    dsurf = np.maximum(np.abs(d - radius) - 2.0 * math.sqrt(3.0), 0.0)
+    desired = np.full((bz, by, bx), levels - 1, np.int16)
+    lim = 0.0
+    for l, b in enumerate(bands[: levels - 1]):
+        lim += b
+        desired = np.where((dsurf <= lim) & (desired > l), l, desired)
+    lm = refine_level_map(nx, ny, nz, levels, desired, periodic)
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    solid = (x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2 <= radius * radius
+    return lm, (~solid).astype(np.uint8)
+
+
+def level_cell_centres(n: int, l: int) -> np.ndarray:
+    """Finest-unit coordinate of the centres of level-l cells along an axis
+    of n finest voxels (finest voxel i sits at i)."""
+    s = 1 << l
+    return np.arange(n >> l, dtype=np.float64) * s + (s - 1) / 2.0

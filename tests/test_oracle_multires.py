@@ -1,0 +1,125 @@
+"""Pins of the multi-resolution FP64 oracle (CPU).
+
+The paper defines explosion and coalescence only in words, so the oracle's
+reading is pinned by properties any correct implementation of it must have:
+exact mass conservation in periodic boxes (the operators move every
+fine-resolution population exactly once), the uniform state as a fixed
+point, reduction to the single-level oracle with one level, and the
+Taylor-Green decay rate across a refined slab.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2503_07898_amd import workloads
+
+
+def blob_level_map(n, levels, centre, radius, band=4.0, periodic=(True, True, True)):
+    nx, ny, nz = n
+    bz, by, bx = nz // 4, ny // 4, nx // 4
+    zc, yc, xc = np.meshgrid(np.arange(bz) * 4 + 1.5, np.arange(by) * 4 + 1.5,
+                             np.arange(bx) * 4 + 1.5, indexing="ij")
+    d = np.sqrt((xc - centre[0]) ** 2 + (yc - centre[1]) ** 2 + (zc - centre[2]) ** 2)
+    desired = np.full((bz, by, bx), levels - 1, np.int16)
+    for l in range(levels - 1):
+        desired = np.where((d <= radius + band * (l + 1)) & (desired > l), l, desired)
+    return workloads.refine_level_map(nx, ny, nz, levels, desired, periodic)
+
+
+def random_state(g, seed, amp_u=0.03, amp_rho=0.01):
+    rng = np.random.default_rng(seed)
+    rho, u = [], []
+    for l in range(g.levels):
+        shp = g.shape(l)
+        rho.append(1 + amp_rho * rng.standard_normal(shp))
+        u.append(amp_u * rng.standard_normal(shp + (3,)))
+    return g.init_equilibrium(rho, u)
+
+
+@pytest.mark.parametrize("levels,n", [(2, (32, 32, 32)), (3, (64, 32, 32))])
+@pytest.mark.parametrize("collision", [0, 1])
+def test_multires_mass_exactly_conserved(orc, levels, n, collision):
+    lm = blob_level_map(n, levels, (n[0] / 2, n[1] / 2, n[2] / 2), 6.0)
+    counts = [int((lm[::1 << l, ::1 << l, ::1 << l] == l).sum()) for l in range(levels)]
+    assert all(c > 0 for c in counts), counts
+    g = orc.MultiresGrid(*n, levels=levels, level_map=lm, tau_coarsest=0.56, collision=collision)
+    f = random_state(g, 3)
+    m0 = g.mass(f)
+    f = g.run(f, 12)
+    m1 = g.mass(f)
+    assert abs(m1 - m0) / m0 < 1e-13, (m0, m1)
+
+
+def test_multires_mass_with_obstacle(orc):
+    n, levels = (64, 32, 32), 3
+    lm = blob_level_map(n, levels, (32, 16, 16), 5.0, band=6.0)
+    z, y, x = np.meshgrid(*(np.arange(k, dtype=float) for k in (n[2], n[1], n[0])), indexing="ij")
+    fluid = ((x - 32) ** 2 + (y - 16) ** 2 + (z - 16) ** 2 > 9.0).astype(np.uint8)
+    g = orc.MultiresGrid(*n, levels=levels, level_map=lm, fluid=fluid, tau_coarsest=0.58)
+    f = random_state(g, 5)
+    f[0][fluid == 0] = 0.0
+    m0 = g.mass(f)
+    f = g.run(f, 10)
+    assert abs(g.mass(f) - m0) / m0 < 1e-13
+
+
+def test_multires_uniform_state_fixed_point(orc):
+    n, levels = (64, 32, 32), 3
+    lm = blob_level_map(n, levels, (32, 16, 16), 6.0)
+    g = orc.MultiresGrid(*n, levels=levels, level_map=lm, tau_coarsest=0.53)
+    u0 = np.array([0.04, -0.01, 0.02])
+    f = g.init_equilibrium([np.full(g.shape(l), 1.02) for l in range(levels)],
+                           [np.broadcast_to(u0, g.shape(l) + (3,)) for l in range(levels)])
+    out = g.run(f, 4)
+    for l in range(levels):
+        a = g.active(l)
+        assert np.max(np.abs(out[l][a] - f[l][a])) < 1e-15
+
+
+def test_multires_single_level_is_single_level_oracle(orc):
+    n = 16
+    rho, u = workloads.taylor_green_2d(n, 0.05)
+    g1 = orc.Grid(n, n, n, tau=0.6)
+    f = g1.init_equilibrium(rho, u)
+    ref = g1.run(f, 9)
+    gm = orc.MultiresGrid(n, n, n, levels=1, level_map=np.zeros((n, n, n), np.uint8), tau_coarsest=0.6)
+    out = gm.run([f], 9)[0]
+    assert np.max(np.abs(out - ref)) < 1e-16
+
+
+def test_multires_taylor_green_decay_across_refined_slab(orc):
+    """2D Taylor-Green vortex (finest wavelength 64 cells) on a periodic box
+    whose middle slab is refined: the amplitude decays as exp(-2 nu k^2 t)
+    (finest units) within 2 % at every level."""
+    n, levels = (64, 64, 16), 2
+    nb = (n[2] // 4, n[1] // 4, n[0] // 4)
+    desired = np.ones(nb, np.int16)
+    desired[:, :, 6:10] = 0  # x in [24, 40) finest
+    lm = workloads.refine_level_map(*n, levels, desired, (True, True, True))
+    tau1 = 0.56
+    g = orc.MultiresGrid(*n, levels=levels, level_map=lm, tau_coarsest=tau1)
+    k = 2 * math.pi / 64
+    u0 = 0.03
+    nu_f = (g.tau(0) - 0.5) / 3.0  # finest-unit viscosity, = 2 nu_coarse
+    rho, u = [], []
+    for l in range(levels):
+        xs = workloads.level_cell_centres(n[0], l)
+        ys = workloads.level_cell_centres(n[1], l)
+        zs = workloads.level_cell_centres(n[2], l)
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        uu = np.zeros(Z.shape + (3,))
+        uu[..., 0] = -u0 * np.cos(k * X) * np.sin(k * Y)
+        uu[..., 1] = u0 * np.sin(k * X) * np.cos(k * Y)
+        rho.append(1 - 0.75 * u0 * u0 * (np.cos(2 * k * X) + np.cos(2 * k * Y)))
+        u.append(uu)
+    f = g.init_equilibrium(rho, u)
+    steps = 60  # coarse steps = 120 finest steps
+    f = g.run(f, steps)
+    decay = math.exp(-2 * nu_f * k * k * 2 * steps)
+    for l, (r, v) in enumerate(g.macroscopic(f)):
+        a = g.active(l)
+        amp = np.sum(v[a] * u[l][a]) / np.sum(u[l][a] * u[l][a])
+        assert abs(amp / decay - 1) < 0.02, (l, amp, decay)
+        err = np.linalg.norm(v[a] - decay * u[l][a]) / np.linalg.norm(decay * u[l][a])
+        assert err < 0.05, (l, err)
