@@ -76,6 +76,29 @@ def taylor_green(lbm, workloads, n=256, collision=1, storage=0):
     return g
 
 
+def multires_sphere(lbm, workloads, storage=0, schedule=1, scale=1):
+    """Flow past a sphere, 3 levels, coarsest 128x64x64 (finest 512x256x256),
+    sphere radius 16 finest cells at (128, 128, 128), finest level within 24
+    cells of the sphere, level 1 within a further 48; regularized inlet and
+    outlet on x, periodic y and z, tau_coarsest = 0.52.  scale=2 doubles
+    every length (the same shape at 8x the voxels)."""
+    n = (512 * scale, 256 * scale, 256 * scale)
+    lm, fluid = workloads.multires_sphere(*n, levels=3, center=(128.0 * scale,) * 3,
+                                          radius=16.0 * scale, bands=(24.0 * scale, 48.0 * scale))
+    faces = {lbm.XMIN: (lbm.BC_REG_VELOCITY, (0.05, 0.0, 0.0)),
+             lbm.XMAX: (lbm.BC_REG_PRESSURE, (1.0, 0.0, 0.0))}
+    g = lbm.Grid(*n, kind=lbm.MULTIRES, levels=3, level_map=lm, fluid=fluid, periodic=(False, True, True),
+                 faces=faces, tau=0.52, storage=storage, schedule=schedule).bind()
+    for l in range(3):
+        N = g.n_level(l)
+        u = np.zeros((3, N))
+        u[0] = 0.05
+        g.init_equilibrium(np.ones(N), u, level=l)
+    # updates per coarse step: every level-l voxel updates 2^(L-1-l) times
+    g.updates_per_step = sum(g.n_level(l) * 2 ** (2 - l) for l in range(3))
+    return g
+
+
 def time_steps(torch, g, steps: int, warmup: int) -> float:
     """Seconds for `steps` lbm_step calls, after `warmup` untimed ones."""
     g.step(warmup)
@@ -166,6 +189,9 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--arms", default="all", choices=["all", "none"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy (torch) 5 times, the reference "
+                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -179,6 +205,15 @@ def main(argv=None) -> int:
         return 1
     lbm.lib()
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 4, "launches": 5}))
+        return 0
+
     # ---------------- headline: cavity 256^3, FP32, disaggregated ----------
     log("cavity 256^3 FP32 disaggregated")
     g = cavity(lbm)
@@ -186,7 +221,7 @@ def main(argv=None) -> int:
     dt, wall = time_steps(torch, g, args.steps, args.warmup)
     mlups = N * args.steps / dt / 1e6
     launches = g.launches()
-    gb, gm, gf, tot = g.index_map(lbm.MAP_GROUPS)
+    _, gb, gm, gf, tot = g.index_map(lbm.MAP_GROUPS)
     k_full = launches.index(int(gf))
     t_full = time_launch(torch, lbm, g, k_full, 50)
     upd_full = int(gf) * 64
@@ -208,7 +243,7 @@ def main(argv=None) -> int:
         def arm(name, make, steps, bytes_per_update):
             log(name)
             gg = make()
-            n_up = gg.n
+            n_up = getattr(gg, "updates_per_step", None) or gg.n
             d, _ = time_steps(torch, gg, steps, 10)
             m = n_up * steps / d / 1e6
             arms[name] = {"MLUPS": round(m, 1),
@@ -224,6 +259,13 @@ def main(argv=None) -> int:
             for sch, nm in ((0, "naive_single_kernel"), (1, "disagg_grouped")):
                 arm(f"tunnel512x256x256_{['f32', 'f16'][st]}_{nm}",
                     lambda st=st, sch=sch: tunnel(lbm, workloads, storage=st, schedule=sch)[0], 50, bpu)
+        for st, bpu in ((0, 152), (1, 76)):
+            for sch, nm in ((0, "unfused_baseline"), (1, "disagg_fused")):
+                arm(f"multires_sphere_c128_{['f32', 'f16'][st]}_{nm}",
+                    lambda st=st, sch=sch: multires_sphere(lbm, workloads, storage=st, schedule=sch), 50, bpu)
+        for sch, nm in ((0, "unfused_baseline"), (1, "disagg_fused")):
+            arm(f"multires_sphere_c256_f32_{nm}",
+                lambda sch=sch: multires_sphere(lbm, workloads, schedule=sch, scale=2), 20, 152)
         arm("taylor_green256_re1600_f32_regularized", lambda: taylor_green(lbm, workloads, collision=1), 100, 152)
         arm("taylor_green256_re1600_f32_bgk", lambda: taylor_green(lbm, workloads, collision=0), 100, 152)
 

@@ -145,8 +145,15 @@ lbm_status lbm_init_equilibrium(lbm_grid *g, int32_t level, const double *rho_de
                                 const double *u_dev, void *stream);
 
 /* Advances n_steps time steps (multires: coarse steps).  Each step is the
- * fused pull collide-and-stream of every group, ping-ponging two population
- * buffers inside the workspace. */
+ * fused pull collide-and-stream of every group, ping-ponging population
+ * buffers inside the workspace.  Multires grids follow the level-recursive
+ * schedule: a level-l step (2^l finest steps, tau_l - 1/2 = (tau - 1/2)
+ * 2^(L-1-l)) runs the finer level's first substep, its own update, then the
+ * finer level's second substep.  Explosion (coarse post-collision values
+ * feeding the finer level) and coalescence (the finer level's streamed
+ * values merging into coarse voxels, as the mean over the 2x2x2 footprint)
+ * are gathers of the jump-group kernel; uniform blocks run the fused kernels
+ * of the single-level grids. */
 lbm_status lbm_step(lbm_grid *g, int32_t n_steps, void *stream);
 
 /* Density and velocity of every fluid voxel of `level` in canonical order,
@@ -169,7 +176,13 @@ lbm_status lbm_write_populations(lbm_grid *g, int32_t level, const double *f_dev
 
 /* Index maps of the internal layout, copied to host memory.  Pass
  * host_out = NULL to query the element count in *count.
- *   LBM_MAP_GROUPS     int64 [4]: blocks in groups (boundary, masked, full, total)
+ *   LBM_MAP_GROUPS     int64 [5]: blocks per group in storage order (jump, boundary,
+ *                      masked, full) and the total; "jump" blocks hold a voxel
+ *                      next to a resolution jump (multires only), "boundary"
+ *                      blocks a voxel next to a moving-wall or regularized face
+ *                      (dense grids: a voxel on any non-periodic face), "masked"
+ *                      blocks pull from some non-fluid source, "full" blocks
+ *                      do not
  *   LBM_MAP_COORDS     int32 [nblocks][3]: block coordinates, in storage order
  *   LBM_MAP_NEIGHBOURS int32 [nblocks][18]: slot of the neighbour block in
  *                      direction 1..18, -1 = none
@@ -185,9 +198,10 @@ typedef enum {
 lbm_status lbm_get_index_map(const lbm_grid *g, int32_t level, lbm_map which, void *host_out,
                              size_t *count);
 
-/* Kernel launches one lbm_step issues per time step, and the blocks each of
- * them covers (for checking the structure of table dissBlock).  kernels_out
- * [max] receives block counts per launch; *n receives the launch count. */
+/* Kernel launches one lbm_step issues per (coarse) time step, and the blocks
+ * each of them covers (for checking the structure of table dissBlock).
+ * blocks_out[max] receives block counts per launch; *n receives the launch
+ * count. */
 lbm_status lbm_step_launches(const lbm_grid *g, int64_t *blocks_out, int32_t max, int32_t *n);
 
 /* Measurement hook: enqueues launch k (0-based, in lbm_step_launches order) of

@@ -41,24 +41,187 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t storage_bytes(int st) { return st == LBM_F32 ? 4 : 2; }
 
+// Device-side layout and time state of one level.
+struct LevelRT {
+  const BlockLevel *L = nullptr;  // null for the lexicographic dense arm
+  const MultiresLevel *M = nullptr;
+  int32_t nx = 0, ny = 0, nz = 0;  // level box in level voxels
+  int64_t S = 0;                   // slots per population plane
+  int64_t n_fluid = 0;
+  double tau = 0.6;
+  int nbuf = 2;
+  size_t off_pop[3] = {0, 0, 0};
+  size_t off_nbr = 0, off_bbm = 0, off_coords = 0, off_canon = 0, off_jtab = 0, off_jlist = 0;
+  int64_t partial_row0 = 0;        // first row of this level in the reduction partials
+  int cur = 0, prev = 2, nxt = 1;  // roles of the population buffers
+  std::vector<int32_t> packed;
+};
+
 }  // namespace
 
 struct lbm_grid {
   lbm_grid_desc desc{};
   std::vector<uint8_t> fluid;
+  std::vector<uint8_t> level_map;
   FaceBC faces[6];
   int state = kCreated;
   bool lex = false;
-  BlockLevel L;
-  int64_t S = 0;        // slots per population plane
-  int64_t n_fluid = 0;
-  // workspace layout (byte offsets)
-  size_t off_pop[2] = {0, 0}, off_nbr = 0, off_bbm = 0, off_coords = 0, off_canon = 0,
-         off_partial = 0, total = 0;
+  BlockLevel single;              // dense / block-sparse
+  std::vector<MultiresLevel> mr;  // multires
+  std::vector<LevelRT> lv;
+  size_t off_partial = 0, total = 0;
+  int64_t partial_rows = 0;
   char *ws = nullptr;
-  int cur = 0;  // index of the buffer holding the current populations
-  std::vector<int32_t> packed_coords;
 };
+
+namespace {
+
+void *pop_ptr(const lbm_grid *g, const LevelRT &r, int role) { return g->ws + r.off_pop[role]; }
+
+StepArgs level_args(const lbm_grid *g, const LevelRT &r) {
+  StepArgs a{};
+  a.S = (uint32_t)r.S;
+  a.nx = r.nx;
+  a.ny = r.ny;
+  a.nz = r.nz;
+  a.omega = (float)(1.0 / r.tau);
+  for (int f = 0; f < 6; ++f) {
+    a.fp.kind[f] = g->faces[f].kind;
+    for (int k = 0; k < 3; ++k) a.fp.val[f][k] = (float)g->faces[f].value[k];
+  }
+  const uint8_t *p = g->desc.periodic;
+  a.fp.periodic = (p[0] ? 1 : 0) | (p[1] ? 2 : 0) | (p[2] ? 4 : 0);
+  if (r.L) {
+    a.nbr = (const int32_t *)(g->ws + r.off_nbr);
+    a.bbm = (const uint64_t *)(g->ws + r.off_bbm);
+    a.coords = (const int32_t *)(g->ws + r.off_coords);
+  }
+  return a;
+}
+
+// Launches of one level update with the level's current buffer roles.
+void level_update(const lbm_grid *g, const std::vector<LevelRT> &lv, int l, int substep,
+                  std::vector<Launch> &out) {
+  const LevelRT &r = lv[l];
+  StepArgs a = level_args(g, r);
+  a.src = pop_ptr(g, r, r.cur);
+  a.dst = pop_ptr(g, r, r.nxt);
+  if (g->lex) {
+    Launch x{};
+    x.kind = kKernelLex;
+    x.fused = 1;
+    x.count = (int32_t)((r.S + 63) / 64);
+    x.args = a;
+    out.push_back(x);
+    return;
+  }
+  const auto &gc = r.L->group_count;
+  const int32_t first[4] = {0, (int32_t)gc[0], (int32_t)(gc[0] + gc[1]), (int32_t)(gc[0] + gc[1] + gc[2])};
+  const int32_t nb = (int32_t)r.L->nblocks;
+  const bool multires = g->desc.kind == LBM_MULTIRES;
+  const bool plain = g->desc.schedule == LBM_PLAIN_SINGLE_KERNEL;
+  auto push = [&](int32_t kind, int32_t fused, int32_t f0, int32_t n) {
+    if (n <= 0) return;
+    Launch x{};
+    x.kind = kind;
+    x.fused = fused;
+    x.first = f0;
+    x.count = n;
+    x.args = a;
+    if (kind == kKernelJump) {
+      MrArgs &m = x.mr;
+      const LevelRT *fr = l > 0 ? &lv[l - 1] : nullptr;
+      const LevelRT *cr = l + 1 < (int)lv.size() ? &lv[l + 1] : nullptr;
+      m.src[0] = pop_ptr(g, r, r.cur);
+      m.src[1] = pop_ptr(g, r, r.prev);
+      m.src[2] = fr ? pop_ptr(g, *fr, fr->cur) : m.src[0];
+      m.src[3] = fr ? pop_ptr(g, *fr, fr->prev) : m.src[0];
+      m.src[4] = cr ? pop_ptr(g, *cr, cr->cur) : m.src[0];
+      m.stride[0] = m.stride[1] = (uint32_t)r.S;
+      m.stride[2] = m.stride[3] = fr ? (uint32_t)fr->S : (uint32_t)r.S;
+      m.stride[4] = cr ? (uint32_t)cr->S : (uint32_t)r.S;
+      m.jtab = (const uint32_t *)(g->ws + r.off_jtab);
+      m.jlist = (const uint32_t *)(g->ws + r.off_jlist);
+      m.phase = substep == 2 ? 1 : 0;
+    }
+    out.push_back(x);
+  };
+  if (!multires) {
+    if (plain) {
+      push(kKernelBoundary, 1, 0, nb);  // the naive single kernel
+    } else {
+      // largest group first; the groups are independent within a step
+      push(kKernelFull, 1, first[3], (int32_t)gc[3]);
+      push(kKernelMasked, 1, first[2], (int32_t)gc[2]);
+      push(kKernelBoundary, 1, first[1], (int32_t)gc[1]);
+    }
+    return;
+  }
+  if (plain && l > 0) {
+    // unfused baseline: streaming kernels, then collision in place
+    push(kKernelJump, 0, first[0], (int32_t)gc[0]);
+    push(kKernelBoundary, 0, first[1], (int32_t)gc[1]);
+    push(kKernelMasked, 0, first[2], (int32_t)gc[2]);
+    push(kKernelFull, 0, first[3], (int32_t)gc[3]);
+    push(kKernelCollide, 1, first[0], (int32_t)gc[0]);
+    push(kKernelCollideHeavy, 1, first[1], (int32_t)gc[1]);
+    push(kKernelCollide, 1, first[2], (int32_t)(gc[2] + gc[3]));
+    return;
+  }
+  // fused collide-and-stream on every group (the jump group through its tables)
+  push(kKernelFull, 1, first[3], (int32_t)gc[3]);
+  push(kKernelMasked, 1, first[2], (int32_t)gc[2]);
+  push(kKernelBoundary, 1, first[1], (int32_t)gc[1]);
+  push(kKernelJump, 1, first[0], (int32_t)gc[0]);
+}
+
+void rotate(LevelRT &r) {
+  if (r.nbuf == 2) {
+    std::swap(r.cur, r.nxt);
+  } else {
+    const int old_prev = r.prev;
+    r.prev = r.cur;
+    r.cur = r.nxt;
+    r.nxt = old_prev;
+  }
+}
+
+// Level-recursive schedule: the finer level's first substep, this level's
+// update, the finer level's second substep, then the buffer rotation.
+void level_schedule(const lbm_grid *g, std::vector<LevelRT> &lv, int l, int substep,
+                    std::vector<Launch> &out) {
+  if (l > 0) level_schedule(g, lv, l - 1, 1, out);
+  level_update(g, lv, l, substep, out);
+  if (l > 0) level_schedule(g, lv, l - 1, 2, out);
+  rotate(lv[l]);
+}
+
+// Launches of one (coarse) step; lv is advanced to the state after it.
+void step_launches(const lbm_grid *g, std::vector<LevelRT> &lv, std::vector<Launch> &out) {
+  out.clear();
+  level_schedule(g, lv, (int)lv.size() - 1, 0, out);
+}
+
+SlotArgs slot_args(const lbm_grid *g, const LevelRT &r) {
+  SlotArgs A{};
+  A.pop_a = pop_ptr(g, r, r.cur);
+  A.pop_b = pop_ptr(g, r, r.nxt);
+  A.S = (uint32_t)r.S;
+  A.nslots = r.S;
+  A.canon = r.L ? (const int32_t *)(g->ws + r.off_canon) : nullptr;
+  A.n = r.n_fluid;
+  A.storage = g->desc.storage;
+  return A;
+}
+
+lbm_status check_level(const lbm_grid *g, int32_t level) {
+  if (level < 0 || level >= (int32_t)g->lv.size()) return fail(LBM_ERR_INVALID_ARG, "level out of range");
+  return LBM_OK;
+}
+
+int32_t coll_code(const lbm_grid *g) { return g->desc.collision == LBM_REGULARIZED ? 1 : 0; }
+
+}  // namespace
 
 extern "C" {
 
@@ -67,24 +230,23 @@ const char *lbm_last_error(void) { return g_err.c_str(); }
 lbm_status lbm_grid_create(const lbm_grid_desc *d, lbm_grid **out) {
   if (!d || !out) return fail(LBM_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
-  if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0)
-    return fail(LBM_ERR_INVALID_ARG, "box sizes must be positive");
-  if (!(d->tau > 0.5) || !std::isfinite(d->tau))
-    return fail(LBM_ERR_INVALID_ARG, "tau must be finite and > 1/2");
-  if (d->storage < LBM_F32 || d->storage > LBM_BF16_SHIFTED)
-    return fail(LBM_ERR_INVALID_ARG, "unknown storage");
-  if (d->collision < LBM_BGK || d->collision > LBM_MLP)
-    return fail(LBM_ERR_INVALID_ARG, "unknown collision");
+  if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(LBM_ERR_INVALID_ARG, "box sizes must be positive");
+  if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return fail(LBM_ERR_INVALID_ARG, "tau must be finite and > 1/2");
+  if (d->storage < LBM_F32 || d->storage > LBM_BF16_SHIFTED) return fail(LBM_ERR_INVALID_ARG, "unknown storage");
+  if (d->collision < LBM_BGK || d->collision > LBM_MLP) return fail(LBM_ERR_INVALID_ARG, "unknown collision");
   if (d->collision == LBM_MLP)
     return fail(LBM_ERR_UNSUPPORTED, "the MLP closure is selected with lbm_set_collision");
   if (d->schedule != LBM_PLAIN_SINGLE_KERNEL && d->schedule != LBM_DISAGG)
     return fail(LBM_ERR_INVALID_ARG, "unknown schedule");
-  if (d->kind == LBM_MULTIRES) return fail(LBM_ERR_UNSUPPORTED, "multires grids are not built yet");
-  if (d->kind != LBM_DENSE && d->kind != LBM_BLOCK_SPARSE)
+  if (d->kind != LBM_DENSE && d->kind != LBM_BLOCK_SPARSE && d->kind != LBM_MULTIRES)
     return fail(LBM_ERR_INVALID_ARG, "unknown grid kind");
-  if (d->num_levels != 1) return fail(LBM_ERR_INVALID_ARG, "dense and block-sparse grids have 1 level");
+  if (d->kind != LBM_MULTIRES && d->num_levels != 1)
+    return fail(LBM_ERR_INVALID_ARG, "dense and block-sparse grids have 1 level");
+  if (d->kind == LBM_MULTIRES && (d->num_levels < 2 || !d->level_map))
+    return fail(LBM_ERR_INVALID_ARG, "multires grids need num_levels >= 2 and a level map");
   const int64_t nv = (int64_t)d->nx * d->ny * d->nz;
-  if (nv * 19 >= ((int64_t)1 << 32)) return fail(LBM_ERR_INVALID_ARG, "box too large for 32-bit offsets");
+  if (d->kind == LBM_DENSE && d->schedule == LBM_PLAIN_SINGLE_KERNEL && nv >= ((int64_t)1 << 31))
+    return fail(LBM_ERR_INVALID_ARG, "box too large for 32-bit slot indices");
   lbm_grid *g = new (std::nothrow) lbm_grid;
   if (!g) return fail(LBM_ERR_OUT_OF_MEMORY, "host allocation failed");
   g->desc = *d;
@@ -92,19 +254,19 @@ lbm_status lbm_grid_create(const lbm_grid_desc *d, lbm_grid **out) {
   g->desc.level_map = nullptr;
   try {
     g->fluid.assign((size_t)nv, 1);
+    if (d->fluid_mask)
+      for (int64_t i = 0; i < nv; ++i) g->fluid[i] = d->fluid_mask[i] ? 1 : 0;
+    if (d->kind == LBM_MULTIRES) g->level_map.assign(d->level_map, d->level_map + nv);
   } catch (...) {
     delete g;
     return fail(LBM_ERR_OUT_OF_MEMORY, "host allocation failed");
   }
-  if (d->fluid_mask) {
-    for (int64_t i = 0; i < nv; ++i) g->fluid[i] = d->fluid_mask[i] ? 1 : 0;
-    if (d->kind == LBM_DENSE) {
-      for (int64_t i = 0; i < nv; ++i)
-        if (!g->fluid[i]) {
-          delete g;
-          return fail(LBM_ERR_INVALID_ARG, "dense grids must be all fluid; use LBM_BLOCK_SPARSE for obstacles");
-        }
-    }
+  if (d->kind == LBM_DENSE && d->fluid_mask) {
+    for (int64_t i = 0; i < nv; ++i)
+      if (!g->fluid[i]) {
+        delete g;
+        return fail(LBM_ERR_INVALID_ARG, "dense grids must be all fluid; use LBM_BLOCK_SPARSE for obstacles");
+      }
   }
   g->lex = d->kind == LBM_DENSE && d->schedule == LBM_PLAIN_SINGLE_KERNEL;
   if (!g->lex && (d->nx % 4 || d->ny % 4 || d->nz % 4)) {
@@ -134,11 +296,11 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
   if (g->state != kCreated) return fail(LBM_ERR_STATE, "grid already committed");
   const lbm_grid_desc &d = g->desc;
   // a voxel may not need two regularized faces
+  auto reg = [&](int f) {
+    return g->faces[f].kind == LBM_BC_REG_VELOCITY || g->faces[f].kind == LBM_BC_REG_PRESSURE;
+  };
   for (int f1 = 0; f1 < 6; ++f1)
     for (int f2 = f1 + 1; f2 < 6; ++f2) {
-      auto reg = [&](int f) {
-        return g->faces[f].kind == LBM_BC_REG_VELOCITY || g->faces[f].kind == LBM_BC_REG_PRESSURE;
-      };
       if (!reg(f1) || !reg(f2) || f1 / 2 == f2 / 2) continue;
       const int a1 = f1 / 2, a2 = f2 / 2;
       const int n[3] = {d.nx, d.ny, d.nz};
@@ -152,44 +314,76 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
           }
     }
   const size_t es = storage_bytes(d.storage);
+  g->lv.clear();
   if (g->lex) {
-    g->S = (int64_t)d.nx * d.ny * d.nz;
-    g->n_fluid = g->S;
-    size_t off = 0;
-    for (int k = 0; k < 2; ++k) {
-      g->off_pop[k] = off;
-      off = align256(off + (size_t)g->S * Q * es);
-    }
-    g->off_partial = off;
-    off = align256(off + (size_t)((g->S + 63) / 64) * 5 * sizeof(double));
-    g->total = off;
-  } else {
-    std::string e = build_block_level(g->L, d.nx, d.ny, d.nz, d.periodic, g->fluid, g->faces,
+    LevelRT r;
+    r.nx = d.nx; r.ny = d.ny; r.nz = d.nz;
+    r.S = (int64_t)d.nx * d.ny * d.nz;
+    r.n_fluid = r.S;
+    r.tau = d.tau;
+    g->lv.push_back(r);
+  } else if (d.kind != LBM_MULTIRES) {
+    std::string e = build_block_level(g->single, d.nx, d.ny, d.nz, d.periodic, g->fluid, g->faces,
                                       d.kind == LBM_DENSE);
     if (!e.empty()) return fail(LBM_ERR_INVALID_ARG, "%s", e.c_str());
-    const BlockLevel &L = g->L;
-    g->S = L.nblocks * 64;
-    g->n_fluid = L.n_fluid;
-    g->packed_coords.resize(L.nblocks);
-    for (int64_t b = 0; b < L.nblocks; ++b)
-      g->packed_coords[b] = L.coords[3 * b] | (L.coords[3 * b + 1] << 10) | (L.coords[3 * b + 2] << 20);
-    size_t off = 0;
-    for (int k = 0; k < 2; ++k) {
-      g->off_pop[k] = off;
-      off = align256(off + (size_t)g->S * Q * es);
+    LevelRT r;
+    r.L = &g->single;
+    r.nx = d.nx; r.ny = d.ny; r.nz = d.nz;
+    r.tau = d.tau;
+    g->lv.push_back(r);
+  } else {
+    std::string e = build_multires(g->mr, d.nx, d.ny, d.nz, d.num_levels, d.periodic, g->level_map,
+                                   g->fluid, g->faces, d.tau);
+    if (!e.empty()) return fail(LBM_ERR_INVALID_ARG, "%s", e.c_str());
+    for (int l = 0; l < d.num_levels; ++l) {
+      LevelRT r;
+      r.L = &g->mr[l].L;
+      r.M = &g->mr[l];
+      r.nx = d.nx >> l; r.ny = d.ny >> l; r.nz = d.nz >> l;
+      r.tau = g->mr[l].tau;
+      r.nbuf = 3;
+      r.cur = 0; r.prev = 1; r.nxt = 2;
+      g->lv.push_back(r);
     }
-    g->off_nbr = off;
-    off = align256(off + (size_t)L.nblocks * 18 * 4);
-    g->off_bbm = off;
-    off = align256(off + (size_t)L.nblocks * 18 * 8);
-    g->off_coords = off;
-    off = align256(off + (size_t)L.nblocks * 4);
-    g->off_canon = off;
-    off = align256(off + (size_t)g->S * 4);
-    g->off_partial = off;
-    off = align256(off + (size_t)L.nblocks * 5 * sizeof(double));
-    g->total = off;
   }
+  // workspace layout
+  size_t off = 0;
+  g->partial_rows = 0;
+  for (LevelRT &r : g->lv) {
+    if (r.L) {
+      r.S = r.L->nblocks * 64;
+      r.n_fluid = r.L->n_fluid;
+      r.packed.resize(r.L->nblocks);
+      for (int64_t b = 0; b < r.L->nblocks; ++b)
+        r.packed[b] = r.L->coords[3 * b] | (r.L->coords[3 * b + 1] << 10) | (r.L->coords[3 * b + 2] << 20);
+    }
+    for (int k = 0; k < r.nbuf; ++k) {
+      r.off_pop[k] = off;
+      off = align256(off + (size_t)r.S * Q * es);
+    }
+    if (r.nbuf == 2) r.off_pop[2] = r.off_pop[0];  // the third role is unused
+    if (r.L) {
+      r.off_nbr = off;
+      off = align256(off + r.L->nbr.size() * 4);
+      r.off_bbm = off;
+      off = align256(off + r.L->bbm.size() * 8);
+      r.off_coords = off;
+      off = align256(off + r.packed.size() * 4);
+      r.off_canon = off;
+      off = align256(off + r.L->canon.size() * 4);
+    }
+    if (r.M) {
+      r.off_jtab = off;
+      off = align256(off + r.M->jtab.size() * 4);
+      r.off_jlist = off;
+      off = align256(off + r.M->jlist.size() * 4 + 4);
+    }
+    r.partial_row0 = g->partial_rows;
+    g->partial_rows += (r.S + 63) / 64;
+  }
+  g->off_partial = off;
+  off = align256(off + (size_t)g->partial_rows * 5 * sizeof(double));
+  g->total = off;
   *bytes = g->total;
   g->state = kCommitted;
   return LBM_OK;
@@ -202,18 +396,23 @@ lbm_status lbm_grid_bind(lbm_grid *g, void *ws, size_t bytes, void *stream) {
   if (((uintptr_t)ws) & 255) return fail(LBM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   g->ws = (char *)ws;
   hipStream_t s = (hipStream_t)stream;
-  if (!g->lex) {
-    const BlockLevel &L = g->L;
-    hipError_t e;
-    // synchronous copies: the host tables may be freed by the caller afterwards
-    if ((e = hipMemcpyAsync(g->ws + g->off_nbr, L.nbr.data(), L.nbr.size() * 4, hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(g->ws + g->off_bbm, L.bbm.data(), L.bbm.size() * 8, hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(g->ws + g->off_coords, g->packed_coords.data(), g->packed_coords.size() * 4,
-                            hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(g->ws + g->off_canon, L.canon.data(), L.canon.size() * 4, hipMemcpyHostToDevice, s)) ||
-        (e = hipStreamSynchronize(s)))
-      return hip_fail(e, "uploading index tables");
+  hipError_t e = hipSuccess;
+  auto up = [&](size_t off, const void *src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(g->ws + off, src, n, hipMemcpyHostToDevice, s);
+  };
+  for (const LevelRT &r : g->lv) {
+    if (!r.L) continue;
+    up(r.off_nbr, r.L->nbr.data(), r.L->nbr.size() * 4);
+    up(r.off_bbm, r.L->bbm.data(), r.L->bbm.size() * 8);
+    up(r.off_coords, r.packed.data(), r.packed.size() * 4);
+    up(r.off_canon, r.L->canon.data(), r.L->canon.size() * 4);
+    if (r.M) {
+      up(r.off_jtab, r.M->jtab.data(), r.M->jtab.size() * 4);
+      up(r.off_jlist, r.M->jlist.data(), r.M->jlist.size() * 4);
+    }
   }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "uploading index tables");
   g->state = kBound;
   return LBM_OK;
 }
@@ -221,88 +420,45 @@ lbm_status lbm_grid_bind(lbm_grid *g, void *ws, size_t bytes, void *stream) {
 lbm_status lbm_num_voxels(const lbm_grid *g, int32_t level, int64_t *n) {
   if (!g || !n) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kCommitted) return fail(LBM_ERR_STATE, "commit first");
-  if (level != 0) return fail(LBM_ERR_INVALID_ARG, "level out of range");
-  *n = g->n_fluid;
+  if (lbm_status s = check_level(g, level)) return s;
+  *n = g->lv[level].n_fluid;
   return LBM_OK;
-}
-
-static SlotArgs slot_args(const lbm_grid *g) {
-  SlotArgs A{};
-  A.pop_a = g->ws + g->off_pop[g->cur];
-  A.pop_b = g->ws + g->off_pop[1 - g->cur];
-  A.S = (uint32_t)g->S;
-  A.nslots = g->S;
-  A.canon = g->lex ? nullptr : (const int32_t *)(g->ws + g->off_canon);
-  A.n = g->n_fluid;
-  A.storage = g->desc.storage;
-  return A;
 }
 
 lbm_status lbm_init_equilibrium(lbm_grid *g, int32_t level, const double *rho, const double *u, void *stream) {
   if (!g || !rho || !u) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kBound) return fail(LBM_ERR_STATE, "bind first");
-  if (level != 0) return fail(LBM_ERR_INVALID_ARG, "level out of range");
-  hipError_t e = launch_init_equilibrium(slot_args(g), rho, u, (hipStream_t)stream);
+  if (lbm_status s = check_level(g, level)) return s;
+  LevelRT &r = g->lv[level];
+  SlotArgs A = slot_args(g, r);
+  hipError_t e = launch_init_equilibrium(A, rho, u, (hipStream_t)stream);
+  if (e == hipSuccess && r.nbuf == 3) {
+    // the buffer one step back starts equal to the current state
+    A.pop_b = pop_ptr(g, r, r.prev);
+    e = launch_init_equilibrium(A, rho, u, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "init_equilibrium");
   g->state = kReady;
   return LBM_OK;
-}
-
-static StepLaunch make_step(const lbm_grid *g) {
-  StepLaunch L{};
-  const lbm_grid_desc &d = g->desc;
-  L.args.S = (uint32_t)g->S;
-  L.args.nx = d.nx;
-  L.args.ny = d.ny;
-  L.args.nz = d.nz;
-  L.args.omega = (float)(1.0 / d.tau);
-  for (int f = 0; f < 6; ++f) {
-    L.args.fp.kind[f] = g->faces[f].kind;
-    for (int a = 0; a < 3; ++a) L.args.fp.val[f][a] = (float)g->faces[f].value[a];
-  }
-  L.args.fp.periodic = (d.periodic[0] ? 1 : 0) | (d.periodic[1] ? 2 : 0) | (d.periodic[2] ? 4 : 0);
-  L.storage = d.storage;
-  L.collision = d.collision == LBM_REGULARIZED ? 1 : 0;
-  L.lex = g->lex;
-  if (!g->lex) {
-    L.args.nbr = (const int32_t *)(g->ws + g->off_nbr);
-    L.args.bbm = (const uint64_t *)(g->ws + g->off_bbm);
-    L.args.coords = (const int32_t *)(g->ws + g->off_coords);
-    const auto &gc = g->L.group_count;
-    if (d.schedule == LBM_PLAIN_SINGLE_KERNEL) {
-      L.nlaunch = 1;
-      L.kind[0] = kKernelBoundary;
-      L.first[0] = 0;
-      L.count[0] = (int32_t)g->L.nblocks;
-    } else {
-      // largest group first; the groups are independent within a step
-      const int32_t first[3] = {0, (int32_t)gc[0], (int32_t)(gc[0] + gc[1])};
-      const int32_t kind[3] = {kKernelBoundary, kKernelMasked, kKernelFull};
-      int order[3] = {2, 1, 0};
-      L.nlaunch = 0;
-      for (int k : order)
-        if (gc[k] > 0) {
-          L.kind[L.nlaunch] = kind[k];
-          L.first[L.nlaunch] = first[k];
-          L.count[L.nlaunch] = (int32_t)gc[k];
-          ++L.nlaunch;
-        }
-    }
-  }
-  return L;
 }
 
 lbm_status lbm_step(lbm_grid *g, int32_t n, void *stream) {
   if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
   if (n < 0) return fail(LBM_ERR_INVALID_ARG, "negative step count");
-  StepLaunch L = make_step(g);
+  std::vector<Launch> launches;
   for (int32_t k = 0; k < n; ++k) {
-    L.args.src = g->ws + g->off_pop[g->cur];
-    L.args.dst = g->ws + g->off_pop[1 - g->cur];
-    hipError_t e = launch_step(L, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "step launch");
-    g->cur = 1 - g->cur;
+    std::vector<LevelRT> next = g->lv;
+    step_launches(g, next, launches);
+    for (const Launch &x : launches) {
+      hipError_t e = launch_one(x, g->desc.storage, coll_code(g), (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "step launch");
+    }
+    for (size_t l = 0; l < g->lv.size(); ++l) {
+      g->lv[l].cur = next[l].cur;
+      g->lv[l].prev = next[l].prev;
+      g->lv[l].nxt = next[l].nxt;
+    }
   }
   return LBM_OK;
 }
@@ -310,33 +466,22 @@ lbm_status lbm_step(lbm_grid *g, int32_t n, void *stream) {
 lbm_status lbm_step_launches(const lbm_grid *g, int64_t *blocks_out, int32_t max, int32_t *n) {
   if (!g || !n) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kCommitted) return fail(LBM_ERR_STATE, "commit first");
-  StepLaunch L = make_step(g);
-  if (g->lex) {
-    *n = 1;
-    if (blocks_out && max >= 1) blocks_out[0] = (g->S + 63) / 64;
-    return LBM_OK;
-  }
-  *n = L.nlaunch;
-  for (int k = 0; k < L.nlaunch && k < max && blocks_out; ++k) blocks_out[k] = L.count[k];
+  std::vector<LevelRT> tmp = g->lv;
+  std::vector<Launch> launches;
+  step_launches(g, tmp, launches);
+  *n = (int32_t)launches.size();
+  for (int k = 0; k < (int)launches.size() && k < max && blocks_out; ++k) blocks_out[k] = launches[k].count;
   return LBM_OK;
 }
 
 lbm_status lbm_launch_group(lbm_grid *g, int32_t k, void *stream) {
   if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
-  StepLaunch L = make_step(g);
-  L.args.src = g->ws + g->off_pop[g->cur];
-  L.args.dst = g->ws + g->off_pop[1 - g->cur];
-  if (g->lex) {
-    if (k != 0) return fail(LBM_ERR_INVALID_ARG, "launch index out of range");
-  } else {
-    if (k < 0 || k >= L.nlaunch) return fail(LBM_ERR_INVALID_ARG, "launch index out of range");
-    L.kind[0] = L.kind[k];
-    L.first[0] = L.first[k];
-    L.count[0] = L.count[k];
-    L.nlaunch = 1;
-  }
-  hipError_t e = launch_step(L, (hipStream_t)stream);
+  std::vector<LevelRT> tmp = g->lv;
+  std::vector<Launch> launches;
+  step_launches(g, tmp, launches);
+  if (k < 0 || k >= (int32_t)launches.size()) return fail(LBM_ERR_INVALID_ARG, "launch index out of range");
+  hipError_t e = launch_one(launches[k], g->desc.storage, coll_code(g), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "launch_group");
   return LBM_OK;
 }
@@ -344,8 +489,8 @@ lbm_status lbm_launch_group(lbm_grid *g, int32_t k, void *stream) {
 lbm_status lbm_read_macroscopic(lbm_grid *g, int32_t level, void *rho, void *u, int32_t f64, void *stream) {
   if (!g || !rho || !u) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
-  if (level != 0) return fail(LBM_ERR_INVALID_ARG, "level out of range");
-  hipError_t e = launch_read_macroscopic(slot_args(g), rho, u, f64 ? 1 : 0, (hipStream_t)stream);
+  if (lbm_status s = check_level(g, level)) return s;
+  hipError_t e = launch_read_macroscopic(slot_args(g, g->lv[level]), rho, u, f64 ? 1 : 0, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "read_macroscopic");
   return LBM_OK;
 }
@@ -353,8 +498,8 @@ lbm_status lbm_read_macroscopic(lbm_grid *g, int32_t level, void *rho, void *u, 
 lbm_status lbm_read_populations(lbm_grid *g, int32_t level, double *f, void *stream) {
   if (!g || !f) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
-  if (level != 0) return fail(LBM_ERR_INVALID_ARG, "level out of range");
-  hipError_t e = launch_read_populations(slot_args(g), f, (hipStream_t)stream);
+  if (lbm_status s = check_level(g, level)) return s;
+  hipError_t e = launch_read_populations(slot_args(g, g->lv[level]), f, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "read_populations");
   return LBM_OK;
 }
@@ -362,10 +507,16 @@ lbm_status lbm_read_populations(lbm_grid *g, int32_t level, double *f, void *str
 lbm_status lbm_write_populations(lbm_grid *g, int32_t level, const double *f, void *stream) {
   if (!g || !f) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kBound) return fail(LBM_ERR_STATE, "bind first");
-  if (level != 0) return fail(LBM_ERR_INVALID_ARG, "level out of range");
+  if (lbm_status s = check_level(g, level)) return s;
   // slots of non-fluid voxels are never read by any kernel, so only fluid
   // slots are written
-  hipError_t e = launch_write_populations(slot_args(g), f, (hipStream_t)stream);
+  LevelRT &r = g->lv[level];
+  SlotArgs A = slot_args(g, r);
+  hipError_t e = launch_write_populations(A, f, (hipStream_t)stream);
+  if (e == hipSuccess && r.nbuf == 3) {
+    A.pop_a = pop_ptr(g, r, r.prev);
+    e = launch_write_populations(A, f, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "write_populations");
   g->state = kReady;
   return LBM_OK;
@@ -374,10 +525,14 @@ lbm_status lbm_write_populations(lbm_grid *g, int32_t level, const double *f, vo
 lbm_status lbm_reduce(lbm_grid *g, double *out5, void *stream) {
   if (!g || !out5) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
-  SlotArgs A = slot_args(g);
   double *partial = (double *)(g->ws + g->off_partial);
-  hipError_t e = launch_reduce_partial(A, 1.0, partial, (hipStream_t)stream);
-  if (e == hipSuccess) e = launch_reduce_final(partial, (A.nslots + 63) / 64, out5, (hipStream_t)stream);
+  hipError_t e = hipSuccess;
+  for (size_t l = 0; l < g->lv.size() && e == hipSuccess; ++l) {
+    const LevelRT &r = g->lv[l];
+    e = launch_reduce_partial(slot_args(g, r), (double)(1ll << (3 * l)), partial + r.partial_row0 * 5,
+                              (hipStream_t)stream);
+  }
+  if (e == hipSuccess) e = launch_reduce_final(partial, g->partial_rows, out5, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "reduce");
   return LBM_OK;
 }
@@ -385,19 +540,17 @@ lbm_status lbm_reduce(lbm_grid *g, double *out5, void *stream) {
 lbm_status lbm_get_index_map(const lbm_grid *g, int32_t level, lbm_map which, void *out, size_t *count) {
   if (!g || !count) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kCommitted) return fail(LBM_ERR_STATE, "commit first");
-  if (level != 0) return fail(LBM_ERR_INVALID_ARG, "level out of range");
+  if (lbm_status s = check_level(g, level)) return s;
   if (g->lex) return fail(LBM_ERR_UNSUPPORTED, "the lexicographic dense arm has no block maps");
-  const BlockLevel &L = g->L;
+  const BlockLevel &L = *g->lv[level].L;
   size_t n = 0;
   switch (which) {
     case LBM_MAP_GROUPS: {
-      n = 4;
+      n = 5;
       if (out) {
         int64_t *o = (int64_t *)out;
-        o[0] = L.group_count[0];
-        o[1] = L.group_count[1];
-        o[2] = L.group_count[2];
-        o[3] = L.nblocks;
+        for (int k = 0; k < 4; ++k) o[k] = L.group_count[k];
+        o[4] = L.nblocks;
       }
       break;
     }

@@ -31,7 +31,7 @@ static bool heavy_face(const FaceBC &f) {
 
 std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
                               const uint8_t periodic[3], const std::vector<uint8_t> &fluid,
-                              const FaceBC faces[6], bool dense) {
+                              const FaceBC faces[6], bool dense, const std::vector<uint8_t> *jump) {
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 4 || ny % 4 || nz % 4)
     return "block grids need positive sizes that are multiples of 4";
   if (nx / 4 >= 1024 || ny / 4 >= 1024 || nz / 4 >= 1024)
@@ -46,14 +46,16 @@ std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
   };
   const int64_t nbtot = (int64_t)L.nbx * L.nby * L.nbz;
 
-  // per-block fluid masks over the whole block box
+  // per-block fluid masks (and jump-voxel flags) over the whole block box
   std::vector<uint64_t> bm(nbtot, 0);
+  std::vector<uint8_t> bj(jump ? nbtot : 0, 0);
   for (int64_t z = 0; z < nz; ++z)
     for (int64_t y = 0; y < ny; ++y)
       for (int64_t x = 0; x < nx; ++x)
         if (fl(x, y, z)) {
           int64_t b = x / 4 + L.nbx * (y / 4 + (int64_t)L.nby * (z / 4));
           bm[b] |= 1ull << ((x & 3) + 4 * (y & 3) + 16 * (z & 3));
+          if (jump && (*jump)[(size_t)(x + nx * (y + (int64_t)ny * z))]) bj[b] = 1;
         }
 
   const int nb3[3] = {L.nbx, L.nby, L.nbz};
@@ -97,6 +99,10 @@ std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
         int64_t b = bid(bx, by, bz);
         if (!bm[b]) continue;
         int g;
+        if (jump && bj[b]) {
+          grp[kGroupJump].push_back({morton_key(bx, by, bz), b});
+          continue;
+        }
         bool shell = (!periodic[0] && (bx == 0 || bx == L.nbx - 1)) ||
                      (!periodic[1] && (by == 0 || by == L.nby - 1)) ||
                      (!periodic[2] && (bz == 0 || bz == L.nbz - 1));

@@ -10,10 +10,17 @@
 namespace lbm {
 
 // Groups of the block layouts, in storage order.  The classification
-// follows the paper's disaggregated design: heavy-boundary blocks, then
-// non-boundary blocks split by whether any voxel pulls from a non-fluid
-// source ("masked") or none does ("full").
-enum BlockGroup : int { kGroupBoundary = 0, kGroupMasked = 1, kGroupFull = 2, kNumGroups = 3 };
+// follows the paper's disaggregated design: blocks next to a resolution jump
+// (multires only), heavy-boundary blocks, then non-boundary blocks split by
+// whether any voxel pulls from a non-fluid source ("masked") or none does
+// ("full").
+enum BlockGroup : int {
+  kGroupJump = 0,
+  kGroupBoundary = 1,
+  kGroupMasked = 2,
+  kGroupFull = 3,
+  kNumGroups = 4
+};
 
 struct FaceBC {
   int32_t kind = LBM_BC_BOUNCE_BACK;
@@ -42,8 +49,45 @@ uint64_t morton_key(uint32_t bx, uint32_t by, uint32_t bz);
 // voxel mask (nx*ny*nz, x fastest).  `dense` selects the shell/interior
 // classification; otherwise blocks with a voxel next to a moving-wall or
 // regularized face form the boundary group.  Returns "" or an error message.
+// `jump` (optional, same shape as fluid) marks voxels next to a resolution
+// jump; blocks holding one form the first group.
 std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
                               const uint8_t periodic[3], const std::vector<uint8_t> &fluid,
-                              const FaceBC faces[6], bool dense);
+                              const FaceBC faces[6], bool dense,
+                              const std::vector<uint8_t> *jump = nullptr);
+
+// ---------------------------------------------------------------- multires
+// Source-list entry of the jump tables: bits 31..29 buffer tag, bit 28 use
+// the opposite population plane, bits 27..0 slot.  Tag kTagList means bits
+// 27..0 index a list of 8 entries whose mean is the value (coalescence).
+enum : uint32_t {
+  kTagLevelCur = 0,
+  kTagLevelPrev = 1,
+  kTagFinerCur = 2,
+  kTagFinerPrev = 3,
+  kTagCoarserCur = 4,
+  kTagList = 7
+};
+constexpr uint32_t kEntryOpp = 1u << 28;
+constexpr uint32_t kSlotMask = (1u << 28) - 1;
+inline uint32_t make_entry(uint32_t tag, uint32_t slot, bool opp) {
+  return (tag << 29) | (opp ? kEntryOpp : 0u) | (slot & kSlotMask);
+}
+
+struct MultiresLevel {
+  BlockLevel L;
+  double tau = 0.6;
+  // [njump][2 phases][19][64] entries (phase 0: first substep of the coarser
+  // level's step, 1: second; the coarsest level uses phase 0 only)
+  std::vector<uint32_t> jtab;
+  std::vector<uint32_t> jlist;  // [nlist][8]
+};
+
+// Validates a multires descriptor and builds every level: active masks,
+// jump voxels, grouped block maps and the jump gather tables.
+std::string build_multires(std::vector<MultiresLevel> &levels, int32_t nx, int32_t ny, int32_t nz,
+                           int32_t num_levels, const uint8_t periodic[3],
+                           const std::vector<uint8_t> &level_map, const std::vector<uint8_t> &fluid,
+                           const FaceBC faces[6], double tau_coarsest);
 
 }  // namespace lbm

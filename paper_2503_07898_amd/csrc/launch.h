@@ -28,20 +28,35 @@ struct StepArgs {
   FaceParams fp;
 };
 
-enum KernelKind : int32_t { kKernelBoundary = 0, kKernelMasked = 1, kKernelFull = 2 };
-
-struct StepLaunch {
-  StepArgs args;
-  int32_t storage;    // lbm_storage
-  int32_t collision;  // 0 BGK, 1 regularized
-  bool lex;           // dense lexicographic single kernel
-  int32_t nlaunch;
-  int32_t kind[4];
-  int32_t first[4];
-  int32_t count[4];
+enum KernelKind : int32_t {
+  kKernelBoundary = 0,      // heavy-boundary group (also the naive single kernel)
+  kKernelMasked = 1,        // non-boundary blocks with bounce-back sources
+  kKernelFull = 2,          // blocks whose every source is fluid
+  kKernelJump = 3,          // multires blocks next to a resolution jump (table gather)
+  kKernelCollide = 4,       // collision only, in place (unfused multires baseline)
+  kKernelCollideHeavy = 5,  // collision only for heavy-boundary blocks
+  kKernelLex = 6            // dense lexicographic single kernel
 };
 
-hipError_t launch_step(const StepLaunch &L, hipStream_t s);
+// Sources of the multires jump gather, indexed by table tag: own level now,
+// own level one step back, finer level now, finer one step back, coarser now.
+struct MrArgs {
+  const void *src[5];
+  uint32_t stride[5];
+  const uint32_t *jtab;   // [njump][2][19][64]
+  const uint32_t *jlist;  // [nlist][8]
+  int32_t phase;          // 0 or 1
+};
+
+struct Launch {
+  int32_t kind;
+  int32_t fused;          // 0: store the gathered (pre-collision) populations only
+  int32_t first, count;   // block range of the launch
+  StepArgs args;
+  MrArgs mr;
+};
+
+hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipStream_t s);
 
 // Utility kernels over a slot range [0, nslots) with an optional canonical
 // map (NULL = identity, every slot fluid).

@@ -13,9 +13,14 @@
 //                halfway bounce-back where the bounce mask says so;
 //   boundary  -- blocks with moving-wall or regularized-face voxels; carries
 //                the per-lane face logic and the regularized reconstruction.
+//   jump      -- multires blocks next to a resolution jump: every source is
+//                read through a precomputed gather table (explosion and
+//                coalescence as pulls), then collided.
 // The single-kernel comparison arm of block-sparse grids launches the
 // boundary kernel over every block.  The dense comparison arm is the
-// lexicographic kernel at the end of this file.
+// lexicographic kernel.  The unfused multires baseline runs the same gathers
+// with FUSED = false (store the pulled populations) followed by the
+// collision-only kernel.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -51,7 +56,7 @@ __device__ __forceinline__ void collide(float (&h)[Q], float omega) {
 }
 
 // ------------------------------------------------------ interior kernels --
-template <class ST, int COLL, bool MASKED>
+template <class ST, int COLL, bool MASKED, bool FUSED>
 __global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, int32_t n) {
   using T = typename ST::T;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -87,14 +92,14 @@ __global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, 
     h[i] = ST::load(src + (size_t)plane * S, slot);
   });
 
-  collide<COLL>(h, a.omega);
+  if constexpr (FUSED) collide<COLL>(h, a.omega);
 
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
 }
 
 // ------------------------------------------------------ boundary kernel --
-template <class ST, int COLL>
+template <class ST, int COLL, bool FUSED>
 __global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, int32_t n) {
   using T = typename ST::T;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -140,11 +145,105 @@ __global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, 
     h[i] = v;
   });
 
-  if (unknown) regularized_face(h, unknown, rface, a.fp, a.omega);
-  else collide<COLL>(h, a.omega);
+  if constexpr (FUSED) {
+    if (unknown) regularized_face(h, unknown, rface, a.fp, a.omega);
+    else collide<COLL>(h, a.omega);
+  }
 
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+}
+
+// ------------------------------------------------- collision-only kernel --
+// In place on a buffer of pulled populations (the unfused multires
+// baseline).  HEAVY blocks re-derive, from their coordinates, which links
+// came from a regularized face and rebuild those populations.
+template <class ST, int COLL, bool HEAVY>
+__global__ __launch_bounds__(256) void k_block_collide(StepArgs a, int32_t g0, int32_t n) {
+  using T = typename ST::T;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  const int lane = threadIdx.x & 63;
+  T *__restrict__ buf = (T *)a.dst;
+  const uint32_t S = a.S;
+  const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
+  float h[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) h[i] = ST::load(buf + (size_t)i * S, own_slot);
+  if constexpr (HEAVY) {
+    const int packed = a.coords[b];
+    const int gx = (packed & 1023) * 4 + (lane & 3);
+    const int gy = ((packed >> 10) & 1023) * 4 + ((lane >> 2) & 3);
+    const int gz = ((packed >> 20) & 1023) * 4 + (lane >> 4);
+    uint32_t unknown = 0;
+    int rface = 0;
+    static_for<1, Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const LinkClass lc = classify_link<i>(a.fp, gx, gy, gz, a.nx, a.ny, a.nz);
+      if (lc.kind == kLinkUnknown) {
+        unknown |= 1u << i;
+        rface = lc.face;
+      }
+    });
+    if (unknown) regularized_face(h, unknown, rface, a.fp, a.omega);
+    else collide<COLL>(h, a.omega);
+  } else {
+    collide<COLL>(h, a.omega);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ST::store(buf + (size_t)i * S, own_slot, h[i]);
+}
+
+// ----------------------------------------------- multires jump kernel ---
+// Blocks next to a resolution jump.  Each (voxel, direction) has one table
+// entry per substep phase: a tagged slot in one of five buffers, or a list
+// of 8 such entries whose mean is taken (coalescence onto the 2x2x2
+// footprint of a coarse voxel).  Explosion, re-entry and coalescence are all
+// gathers, so no atomics and no second pass are needed.
+template <class ST>
+__device__ __forceinline__ float mr_fetch(const MrArgs &m, uint32_t e, int plane, int opp_plane) {
+  using T = typename ST::T;
+  const uint32_t tag = e >> 29;
+  const uint32_t slot = e & ((1u << 28) - 1u);
+  const int pl = (e >> 28) & 1u ? opp_plane : plane;
+  const T *base = (const T *)m.src[0];
+  uint32_t stride = m.stride[0];
+#pragma unroll
+  for (int t = 1; t < 5; ++t) {
+    base = tag == (uint32_t)t ? (const T *)m.src[t] : base;
+    stride = tag == (uint32_t)t ? m.stride[t] : stride;
+  }
+  return ST::load(base + (size_t)pl * stride, slot);
+}
+
+template <class ST, int COLL, bool FUSED>
+__global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g0, int32_t n) {
+  using T = typename ST::T;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  const int lane = threadIdx.x & 63;
+  T *__restrict__ dst = (T *)a.dst;
+  const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
+  const uint32_t *tab = m.jtab + ((size_t)b * 2 + m.phase) * Q * 64 + lane;
+  float h[Q];
+  static_for<0, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const uint32_t e = tab[i * 64];
+    if ((e >> 29) == 7u) {
+      const uint32_t *lst = m.jlist + (size_t)(e & ((1u << 28) - 1u)) * 8;
+      float sum = mr_fetch<ST>(m, lst[0], i, kOpp[i]);
+#pragma unroll
+      for (int k = 1; k < 8; ++k) sum = sum + mr_fetch<ST>(m, lst[k], i, kOpp[i]);
+      h[i] = sum * 0.125f;
+    } else {
+      h[i] = mr_fetch<ST>(m, e, i, kOpp[i]);
+    }
+  });
+  if constexpr (FUSED) collide<COLL>(h, a.omega);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * a.S, own_slot, h[i]);
 }
 
 // ---------------------------------------------- dense lexicographic arm ---
@@ -198,40 +297,52 @@ __global__ __launch_bounds__(256) void k_lex(StepArgs a) {
 
 // --------------------------------------------------------------- launch --
 template <class ST, int COLL>
-static hipError_t launch_step_t(const StepLaunch &L, hipStream_t s) {
-  if (L.lex) {
+static hipError_t launch_t(const Launch &L, hipStream_t s) {
+  if (L.kind == kKernelLex) {
     dim3 blk(64, 4, 1);
     dim3 grd((L.args.nx + 63) / 64, (L.args.ny + 3) / 4, L.args.nz);
     hipLaunchKernelGGL((k_lex<ST, COLL>), grd, blk, 0, s, L.args);
     return hipGetLastError();
   }
-  for (int k = 0; k < L.nlaunch; ++k) {
-    const int32_t g0 = L.first[k], n = L.count[k];
-    if (n <= 0) continue;
-    const int nwg = (n + 3) / 4;
-    switch (L.kind[k]) {
-      case kKernelFull:
-        hipLaunchKernelGGL((k_block_interior<ST, COLL, false>), dim3(nwg), dim3(256), 0, s, L.args, g0, n);
-        break;
-      case kKernelMasked:
-        hipLaunchKernelGGL((k_block_interior<ST, COLL, true>), dim3(nwg), dim3(256), 0, s, L.args, g0, n);
-        break;
-      default:
-        hipLaunchKernelGGL((k_block_boundary<ST, COLL>), dim3(nwg), dim3(256), 0, s, L.args, g0, n);
-        break;
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  const int32_t g0 = L.first, n = L.count;
+  if (n <= 0) return hipSuccess;
+  const dim3 grd((n + 3) / 4), blk(256);
+  const bool f = L.fused != 0;
+  switch (L.kind) {
+    case kKernelFull:
+      if (f) hipLaunchKernelGGL((k_block_interior<ST, COLL, false, true>), grd, blk, 0, s, L.args, g0, n);
+      else hipLaunchKernelGGL((k_block_interior<ST, COLL, false, false>), grd, blk, 0, s, L.args, g0, n);
+      break;
+    case kKernelMasked:
+      if (f) hipLaunchKernelGGL((k_block_interior<ST, COLL, true, true>), grd, blk, 0, s, L.args, g0, n);
+      else hipLaunchKernelGGL((k_block_interior<ST, COLL, true, false>), grd, blk, 0, s, L.args, g0, n);
+      break;
+    case kKernelBoundary:
+      if (f) hipLaunchKernelGGL((k_block_boundary<ST, COLL, true>), grd, blk, 0, s, L.args, g0, n);
+      else hipLaunchKernelGGL((k_block_boundary<ST, COLL, false>), grd, blk, 0, s, L.args, g0, n);
+      break;
+    case kKernelJump:
+      if (f) hipLaunchKernelGGL((k_mr_jump<ST, COLL, true>), grd, blk, 0, s, L.args, L.mr, g0, n);
+      else hipLaunchKernelGGL((k_mr_jump<ST, COLL, false>), grd, blk, 0, s, L.args, L.mr, g0, n);
+      break;
+    case kKernelCollide:
+      hipLaunchKernelGGL((k_block_collide<ST, COLL, false>), grd, blk, 0, s, L.args, g0, n);
+      break;
+    case kKernelCollideHeavy:
+      hipLaunchKernelGGL((k_block_collide<ST, COLL, true>), grd, blk, 0, s, L.args, g0, n);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
-hipError_t launch_step(const StepLaunch &L, hipStream_t s) {
-  const bool reg = L.collision == kCollRegularized;
-  switch (L.storage) {
-    case LBM_F32: return reg ? launch_step_t<StoreF32, kCollRegularized>(L, s) : launch_step_t<StoreF32, kCollBGK>(L, s);
-    case LBM_F16_SHIFTED: return reg ? launch_step_t<StoreF16, kCollRegularized>(L, s) : launch_step_t<StoreF16, kCollBGK>(L, s);
-    case LBM_BF16_SHIFTED: return reg ? launch_step_t<StoreBF16, kCollRegularized>(L, s) : launch_step_t<StoreBF16, kCollBGK>(L, s);
+hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipStream_t s) {
+  const bool reg = collision == kCollRegularized;
+  switch (storage) {
+    case LBM_F32: return reg ? launch_t<StoreF32, kCollRegularized>(L, s) : launch_t<StoreF32, kCollBGK>(L, s);
+    case LBM_F16_SHIFTED: return reg ? launch_t<StoreF16, kCollRegularized>(L, s) : launch_t<StoreF16, kCollBGK>(L, s);
+    case LBM_BF16_SHIFTED: return reg ? launch_t<StoreBF16, kCollRegularized>(L, s) : launch_t<StoreBF16, kCollBGK>(L, s);
   }
   return hipErrorInvalidValue;
 }

@@ -166,8 +166,8 @@ def lbm_get_index_map(g, level: int, which: int) -> np.ndarray:
 
 def lbm_step_launches(g) -> list[int]:
     n = ctypes.c_int32()
-    buf = (ctypes.c_int64 * 8)()
-    check(lib().lbm_step_launches(g, buf, 8, ctypes.byref(n)))
+    buf = (ctypes.c_int64 * 256)()
+    check(lib().lbm_step_launches(g, buf, 256, ctypes.byref(n)))
     return [int(buf[k]) for k in range(n.value)]
 
 
@@ -185,7 +185,9 @@ def lbm_grid_destroy(g) -> None:
 class Grid:
     """One liblbm grid with its device workspace held as a torch tensor.
 
-    fluid: uint8 (nz, ny, nx) or None; faces: {face: (kind, value3)}.
+    fluid: uint8 (nz, ny, nx) or None; faces: {face: (kind, value3)};
+    multires grids also take level_map (uint8 (nz, ny, nx), 0 = finest) and
+    levels.  Per-level calls take `level` (default 0).
     """
     nx: int
     ny: int
@@ -199,6 +201,8 @@ class Grid:
     schedule: int = DISAGG
     faces: dict = field(default_factory=dict)
     device: str = "cuda"
+    level_map: np.ndarray | None = None
+    levels: int = 1
 
     def __post_init__(self):
         d = GridDesc()
@@ -206,7 +210,12 @@ class Grid:
         d.nx, d.ny, d.nz = self.nx, self.ny, self.nz
         for a in range(3):
             d.periodic[a] = 1 if self.periodic[a] else 0
-        d.num_levels = 1
+        d.num_levels = self.levels
+        self._lmap = None
+        if self.level_map is not None:
+            self._lmap = np.ascontiguousarray(self.level_map, np.uint8)
+            assert self._lmap.shape == (self.nz, self.ny, self.nx)
+            d.level_map = self._lmap.ctypes.data
         self._mask = None
         if self.fluid is not None:
             self._mask = np.ascontiguousarray(self.fluid, np.uint8)
@@ -230,36 +239,42 @@ class Grid:
     def n(self) -> int:
         return lbm_num_voxels(self.h, 0)
 
-    def init_equilibrium(self, rho, u):
+    def n_level(self, level: int) -> int:
+        return lbm_num_voxels(self.h, level)
+
+    def init_equilibrium(self, rho, u, level: int = 0):
         """rho [N], u [3][N] canonical order (numpy or torch, converted to FP64 on device)."""
         import torch
+        n = self.n_level(level)
         r = torch.as_tensor(np.asarray(rho, np.float64).reshape(-1)).to(self.device)
         v = torch.as_tensor(np.asarray(u, np.float64).reshape(3, -1)).contiguous().to(self.device)
-        assert r.numel() == self.n and v.shape[1] == self.n
-        lbm_init_equilibrium(self.h, 0, r.data_ptr(), v.data_ptr())
+        assert r.numel() == n and v.shape[1] == n
+        lbm_init_equilibrium(self.h, level, r.data_ptr(), v.data_ptr())
         torch.cuda.current_stream().synchronize()
 
     def step(self, n: int = 1):
         lbm_step(self.h, n)
 
-    def macroscopic(self, f64: bool = True):
+    def macroscopic(self, f64: bool = True, level: int = 0):
         import torch
         dt = torch.float64 if f64 else torch.float32
-        rho = torch.empty(self.n, dtype=dt, device=self.device)
-        u = torch.empty(3, self.n, dtype=dt, device=self.device)
-        lbm_read_macroscopic(self.h, 0, rho.data_ptr(), u.data_ptr(), f64)
+        n = self.n_level(level)
+        rho = torch.empty(n, dtype=dt, device=self.device)
+        u = torch.empty(3, n, dtype=dt, device=self.device)
+        lbm_read_macroscopic(self.h, level, rho.data_ptr(), u.data_ptr(), f64)
         return rho, u
 
-    def populations(self):
+    def populations(self, level: int = 0):
         import torch
-        f = torch.empty(19, self.n, dtype=torch.float64, device=self.device)
-        lbm_read_populations(self.h, 0, f.data_ptr())
+        f = torch.empty(19, self.n_level(level), dtype=torch.float64, device=self.device)
+        lbm_read_populations(self.h, level, f.data_ptr())
         return f
 
-    def write_populations(self, f):
+    def write_populations(self, f, level: int = 0):
         import torch
-        t = torch.as_tensor(f, dtype=torch.float64).reshape(19, self.n).contiguous().to(self.device)
-        lbm_write_populations(self.h, 0, t.data_ptr())
+        n = self.n_level(level)
+        t = torch.as_tensor(f, dtype=torch.float64).reshape(19, n).contiguous().to(self.device)
+        lbm_write_populations(self.h, level, t.data_ptr())
         torch.cuda.current_stream().synchronize()
 
     def reduce(self):
@@ -268,8 +283,8 @@ class Grid:
         lbm_reduce(self.h, out.data_ptr())
         return out
 
-    def index_map(self, which: int) -> np.ndarray:
-        return lbm_get_index_map(self.h, 0, which)
+    def index_map(self, which: int, level: int = 0) -> np.ndarray:
+        return lbm_get_index_map(self.h, level, which)
 
     def launches(self) -> list[int]:
         return lbm_step_launches(self.h)

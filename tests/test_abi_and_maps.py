@@ -126,8 +126,9 @@ def test_index_maps_bit_exact(orc, case, seed):
               for k in kinds]
     ref = orc.build_block_maps(*n, periodic, fluid, okinds, dense)
     groups = g.index_map(lbm.MAP_GROUPS)
-    assert tuple(groups[:3]) == ref["groups"]
-    nb = int(groups[3])
+    assert groups[0] == 0  # no resolution jumps on a single-level grid
+    assert tuple(groups[1:4]) == ref["groups"]
+    nb = int(groups[4])
     assert np.array_equal(g.index_map(lbm.MAP_COORDS).reshape(nb, 3), ref["coords"])
     assert np.array_equal(g.index_map(lbm.MAP_NEIGHBOURS).reshape(nb, 18), ref["nbr"])
     assert np.array_equal(g.index_map(lbm.MAP_FLUIDMASK), ref["fmask"])
@@ -161,7 +162,7 @@ def test_launch_structure_table_dissBlock():
                   device="cpu")
     naive = lbm.Grid(*n, schedule=lbm.PLAIN_SINGLE_KERNEL, **common)
     disagg = lbm.Grid(*n, schedule=lbm.DISAGG, **common)
-    gb, gm, gf, total = disagg.index_map(lbm.MAP_GROUPS)
+    _, gb, gm, gf, total = disagg.index_map(lbm.MAP_GROUPS)
     assert naive.launches() == [total]
     assert sorted(disagg.launches()) == sorted(x for x in (gb, gm, gf) if x > 0)
     assert gb == 2 * (n[1] // 4) * (n[2] // 4)  # inlet and outlet block layers

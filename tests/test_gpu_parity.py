@@ -134,7 +134,7 @@ def test_cavity_plain_vs_disagg_vs_oracle(orc, storage, bar):
         assert err < bar
         pops.append(g.populations().cpu().numpy())
         if sch == lbm.DISAGG:
-            gb, gm, gf, tot = g.index_map(lbm.MAP_GROUPS)
+            _, gb, gm, gf, tot = g.index_map(lbm.MAP_GROUPS)
             assert gb == 8 ** 3 - 6 ** 3 and gf == 6 ** 3 and gm == 0
         g.close()
     assert np.array_equal(pops[0], pops[1])
