@@ -218,3 +218,24 @@ def level_cell_centres(n: int, l: int) -> np.ndarray:
     of n finest voxels (finest voxel i sits at i)."""
     s = 1 << l
     return np.arange(n >> l, dtype=np.float64) * s + (s - 1) / 2.0
+
+
+# --------------------------------------------------------- learned closure ---
+
+def mlp_he_uniform(seed: int, sizes=(19, 64, 64, 19)):
+    """Initial weights of the closure network: He-uniform
+    U(-sqrt(6/fan_in), +sqrt(6/fan_in)) per layer from default_rng(seed), zero
+    biases.  Returns [W1, b1, W2, b2, W3, b3] as float64 arrays, W_k shaped
+    (fan_in, fan_out)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        lim = math.sqrt(6.0 / a)
+        out.append(rng.uniform(-lim, lim, (a, b)))
+        out.append(np.zeros(b))
+    return out
+
+
+def sample_indices(seed: int, n: int, population: int) -> np.ndarray:
+    """n indices drawn uniformly with replacement from range(population)."""
+    return np.random.default_rng(seed).integers(0, population, n, dtype=np.int64)

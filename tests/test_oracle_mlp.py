@@ -1,0 +1,131 @@
+"""Pins of the FP64 closure oracle (CPU): gradients against central finite
+differences, the projection's exact moments, GELU against its derivative and
+the erf form it approximates, the closure assembly against the regularized
+operator, and Adam's closed-form first step."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2503_07898_amd import workloads
+
+
+@pytest.fixture(scope="module")
+def mlp(orc):
+    from oracle import mlp
+    return mlp
+
+
+def make_params(mlp, seed=0):
+    W = workloads.mlp_he_uniform(seed)
+    rng = np.random.default_rng(seed + 1)
+    for k in (1, 3, 5):
+        W[k] = 0.1 * rng.standard_normal(W[k].shape)
+    return mlp.Params(*W, in_mean=0.01 * rng.standard_normal(19), in_std=0.5 + rng.random(19),
+                      out_mean=1e-3 * rng.standard_normal(19), out_std=0.01 + 0.02 * rng.random(19))
+
+
+def sample_populations(orc, n, seed, amp=0.05):
+    rng = np.random.default_rng(seed)
+    f = np.zeros((n, 19))
+    for k in range(n):
+        f[k] = orc.equilibrium(rng.uniform(0.95, 1.05), rng.uniform(-0.08, 0.08, 3))
+        f[k] *= 1 + amp * rng.standard_normal(19)
+    return f
+
+
+def test_gradients_match_central_differences(orc, mlp):
+    p = make_params(mlp)
+    f = sample_populations(orc, 6, 1)
+    g = mlp.closure_inputs(f)
+    t = mlp.regularized_target(f)
+    grads = mlp.backward(p, g, t)
+    h = 1e-6
+    for name, gr in zip(mlp.Params.TRAINED, grads):
+        w = getattr(p, name)
+        num = np.zeros_like(w)
+        flat = w.reshape(-1)
+        nf = num.reshape(-1)
+        for k in range(flat.size):
+            old = flat[k]
+            flat[k] = old + h
+            lp = mlp.loss(p, g, t)
+            flat[k] = old - h
+            lm = mlp.loss(p, g, t)
+            flat[k] = old
+            nf[k] = (lp - lm) / (2 * h)
+        err = np.linalg.norm(num - gr) / max(np.linalg.norm(gr), 1e-30)
+        assert err < 1e-6, (name, err)
+
+
+def test_projection_moments_and_idempotence(orc, mlp):
+    c, w = mlp.lattice()
+    rng = np.random.default_rng(2)
+    y = rng.standard_normal((50, 19))
+    py = mlp.project(y)
+    assert np.max(np.abs(py.sum(-1))) < 1e-14
+    assert np.max(np.abs(py @ c)) < 1e-14
+    assert np.allclose(mlp.project(py), py, atol=1e-15, rtol=0)
+    # the regularized target already carries no mass or momentum
+    f = sample_populations(orc, 20, 3)
+    t = mlp.regularized_target(f)
+    assert np.allclose(mlp.project(t), t, atol=1e-16, rtol=0)
+    # P as a matrix equals P as a function
+    assert np.allclose(y @ mlp.projection_matrix().T, py, atol=1e-14, rtol=0)
+
+
+def test_gelu(mlp):
+    x = np.linspace(-6, 6, 241)
+    h = 1e-6
+    num = (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h)
+    assert np.max(np.abs(num - mlp.gelu_grad(x))) < 1e-8
+    exact = np.array([0.5 * v * (1 + math.erf(v / math.sqrt(2))) for v in x])
+    assert np.max(np.abs(mlp.gelu(x) - exact)) < 1e-3  # the tanh form's known accuracy
+
+
+def test_closure_assembly_equals_regularized_with_exact_output(orc, mlp):
+    p = make_params(mlp)
+    p.in_std[:] = 1e3  # keep inputs far inside the fallback limit
+    f = sample_populations(orc, 12, 4)
+    t = mlp.regularized_target(f)
+    for tau in (0.51, 0.6, 0.9):
+        out, fell = mlp.collide(p, f, tau, y_override=t)
+        assert not fell.any()
+        ref = np.array([orc.collide_regularized(fk, tau) for fk in f])
+        assert np.max(np.abs(out - ref)) < 1e-15
+
+
+def test_closure_fallback_and_conservation(orc, mlp):
+    p = make_params(mlp)
+    f = sample_populations(orc, 30, 5, amp=0.1)
+    out, fell = mlp.collide(p, f, 0.6)
+    c, _ = mlp.lattice()
+    assert np.allclose(out.sum(-1), f.sum(-1), atol=1e-14, rtol=0)
+    assert np.allclose(out @ c, f @ c, atol=1e-14, rtol=0)
+    p.in_std[:] = 1e-4  # every standardized input is huge -> every voxel falls back
+    out2, fell2 = mlp.collide(p, f, 0.6)
+    assert fell2.all()
+    ref = np.array([orc.collide_regularized(fk, 0.6) for fk in f])
+    assert np.max(np.abs(out2 - ref)) < 1e-16
+
+
+def test_adam_first_step_closed_form(mlp):
+    rng = np.random.default_rng(6)
+    w = [rng.standard_normal((5, 4))]
+    g = [rng.standard_normal((5, 4))]
+    w0 = w[0].copy()
+    opt = mlp.Adam(lr=1e-3)
+    m, v = [np.zeros_like(w[0])], [np.zeros_like(w[0])]
+    opt.step(w, g, m, v, 1)
+    assert np.allclose(w[0], w0 - 1e-3 * g[0] / (np.abs(g[0]) + 1e-8), atol=1e-15, rtol=0)
+
+
+def test_bf16_rounding_reference(mlp):
+    # nearest-even at the 8th significant bit, checked on hand-picked values
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 3.14159265])
+    out = mlp.bf16_round(vals)
+    assert out[0] == 1.0
+    assert out[1] == 1.0                    # tie -> even mantissa
+    assert out[2] == 1.0 + 2 ** -6          # tie -> even (up)
+    assert out[3] == -2.5
+    assert out[4] == 3.140625
