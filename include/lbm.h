@@ -204,6 +204,63 @@ lbm_status lbm_get_index_map(const lbm_grid *g, int32_t level, lbm_map which, vo
  * count. */
 lbm_status lbm_step_launches(const lbm_grid *g, int64_t *blocks_out, int32_t max, int32_t *n);
 
+/* ------------------------------------------------- learned collision closure
+ * A 19-64-64-19 perceptron with tanh-form GELU activations (an addition of
+ * this library; the paper has no learned component).  Input: the
+ * standardized non-equilibrium state g = f/rho - w of a voxel; output: an
+ * estimate y of the regularized operator's non-equilibrium part per unit
+ * density, projected to zero mass and momentum, P(y); post-collision state
+ * f* = f^eq + (1 - 1/tau) rho P(y).  Inference and training forward run on
+ * the matrix cores in bfloat16 with FP32 accumulation; FP32 master weights
+ * are trained with Adam (beta 0.9 / 0.999, eps 1e-8) on the mean squared
+ * error of P(y) against f1/rho.  Parameters are flat FP32 arrays of
+ * LBM_MLP_PARAMS values: W1 [19][64], b1 [64], W2 [64][64], b2 [64],
+ * W3 [64][19], b3 [19] (row-major, W_k indexed [input][output]).
+ * Standardization: 128 floats, in_mean [32] | in_inv_std [32] |
+ * out_std [32] | out_mean [32] (first 19 of each used). */
+#define LBM_MLP_PARAMS 6675
+#define LBM_MLP_BATCH_MAX 8192
+typedef struct lbm_mlp lbm_mlp;
+
+/* Creates a closure object and reports the device buffer it needs. */
+lbm_status lbm_mlp_create(lbm_mlp **out, size_t *bytes_needed);
+/* Binds caller-owned device memory (256-byte aligned); clears optimizer
+ * state and the fallback counter, sets identity standardization. */
+lbm_status lbm_mlp_bind(lbm_mlp *m, void *device_buffer, size_t bytes, void *stream);
+/* Copies LBM_MLP_PARAMS host floats into the master weights (synchronous). */
+lbm_status lbm_mlp_set_params(lbm_mlp *m, const float *host_params, void *stream);
+lbm_status lbm_mlp_get_params(lbm_mlp *m, float *host_params, void *stream);
+/* 128 host floats (layout above), synchronous. */
+lbm_status lbm_mlp_set_standardization(lbm_mlp *m, const float *host_stdz, void *stream);
+lbm_status lbm_mlp_get_standardization(lbm_mlp *m, float *host_stdz, void *stream);
+/* Per-component mean and standard deviation of the inputs g and targets
+ * f1/rho over n populations f_dev [n][19] (FP32, unshifted). */
+lbm_status lbm_mlp_fit_standardization(lbm_mlp *m, const float *f_dev, int64_t n, void *stream);
+/* Network output y (de-standardized, before projection) for n populations. */
+lbm_status lbm_mlp_forward(lbm_mlp *m, const float *f_dev, int64_t n, float *y_dev, void *stream);
+/* Loss and gradients of one batch (n <= LBM_MLP_BATCH_MAX): grads_dev
+ * [LBM_MLP_PARAMS] (may be NULL), loss_dev one double (may be NULL). */
+lbm_status lbm_mlp_gradients(lbm_mlp *m, const float *f_dev, int64_t n, float *grads_dev,
+                             double *loss_dev, void *stream);
+/* One training step: gradients of the batch, then Adam step t (t >= 1). */
+lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f_dev, int64_t n, float lr, int32_t t,
+                              double *loss_dev, void *stream);
+/* Voxels that fell back to the regularized operator since bind/reset. */
+lbm_status lbm_mlp_fallbacks(lbm_mlp *m, uint64_t *host_count, int32_t reset, void *stream);
+lbm_status lbm_mlp_destroy(lbm_mlp *m);
+
+/* Switches a committed dense or block-sparse grid (disaggregated schedule)
+ * to another collision operator.  LBM_MLP needs a bound closure and applies
+ * it to the non-boundary groups; blocks of the boundary group then use the
+ * regularized operator.  The closure must outlive its use by the grid. */
+lbm_status lbm_set_collision(lbm_grid *g, lbm_collision c, const lbm_mlp *m);
+
+/* n populations (FP32, unshifted, [n][19]) of fluid voxels drawn uniformly
+ * (with replacement, counter-based splitmix64 stream from `seed`) from the
+ * non-boundary groups of `level` -- the training data of the closure. */
+lbm_status lbm_sample_populations(lbm_grid *g, int32_t level, uint64_t seed, int64_t n, float *f_dev,
+                                  void *stream);
+
 /* Measurement hook: enqueues launch k (0-based, in lbm_step_launches order) of
  * one step on its own -- it reads the current populations and writes the
  * other buffer, which does not become current.  Lets a caller time one

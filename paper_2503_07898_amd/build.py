@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "builder.cpp", "multires_builder.cpp", "step_kernels.hip", "util_kernels.hip"]
+SOURCES = ["api.cpp", "builder.cpp", "multires_builder.cpp", "step_kernels.hip", "util_kernels.hip", "mlp_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

@@ -14,6 +14,7 @@
 #include "grid.h"
 #include "launch.h"
 #include "lattice.h"
+#include "mlp_device.h"
 
 using namespace lbm;
 
@@ -51,7 +52,7 @@ struct LevelRT {
   double tau = 0.6;
   int nbuf = 2;
   size_t off_pop[3] = {0, 0, 0};
-  size_t off_nbr = 0, off_bbm = 0, off_coords = 0, off_canon = 0, off_jtab = 0, off_jlist = 0;
+  size_t off_nbr = 0, off_bbm = 0, off_coords = 0, off_canon = 0, off_jtab = 0, off_jlist = 0, off_fmask = 0;
   int64_t partial_row0 = 0;        // first row of this level in the reduction partials
   int cur = 0, prev = 2, nxt = 1;  // roles of the population buffers
   std::vector<int32_t> packed;
@@ -59,8 +60,18 @@ struct LevelRT {
 
 }  // namespace
 
+struct lbm_mlp {
+  size_t total = 0;
+  size_t off_params = 0, off_m = 0, off_v = 0, off_grads = 0, off_w = 0, off_bias = 0, off_stdz = 0,
+         off_fb = 0, off_save = 0, off_dyt = 0, off_dz1 = 0, off_dz2 = 0, off_partial = 0, off_loss = 0;
+  char *ws = nullptr;
+  MlpBuffers B{};
+};
+
 struct lbm_grid {
   lbm_grid_desc desc{};
+  int32_t collision = LBM_BGK;
+  const lbm_mlp *mlp = nullptr;
   std::vector<uint8_t> fluid;
   std::vector<uint8_t> level_map;
   FaceBC faces[6];
@@ -95,6 +106,13 @@ StepArgs level_args(const lbm_grid *g, const LevelRT &r) {
     a.nbr = (const int32_t *)(g->ws + r.off_nbr);
     a.bbm = (const uint64_t *)(g->ws + r.off_bbm);
     a.coords = (const int32_t *)(g->ws + r.off_coords);
+    a.fmask = (const uint64_t *)(g->ws + r.off_fmask);
+  }
+  if (g->mlp) {
+    a.mlp_w = g->mlp->B.wpacked;
+    a.mlp_bias = g->mlp->B.bias;
+    a.mlp_stdz = g->mlp->B.stdz;
+    a.mlp_fallbacks = g->mlp->B.fallbacks;
   }
   return a;
 }
@@ -219,7 +237,9 @@ lbm_status check_level(const lbm_grid *g, int32_t level) {
   return LBM_OK;
 }
 
-int32_t coll_code(const lbm_grid *g) { return g->desc.collision == LBM_REGULARIZED ? 1 : 0; }
+int32_t coll_code(const lbm_grid *g) {
+  return g->collision == LBM_MLP ? 2 : (g->collision == LBM_REGULARIZED ? 1 : 0);
+}
 
 }  // namespace
 
@@ -250,6 +270,7 @@ lbm_status lbm_grid_create(const lbm_grid_desc *d, lbm_grid **out) {
   lbm_grid *g = new (std::nothrow) lbm_grid;
   if (!g) return fail(LBM_ERR_OUT_OF_MEMORY, "host allocation failed");
   g->desc = *d;
+  g->collision = d->collision;
   g->desc.fluid_mask = nullptr;
   g->desc.level_map = nullptr;
   try {
@@ -371,6 +392,8 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
       off = align256(off + r.packed.size() * 4);
       r.off_canon = off;
       off = align256(off + r.L->canon.size() * 4);
+      r.off_fmask = off;
+      off = align256(off + r.L->fmask.size() * 8);
     }
     if (r.M) {
       r.off_jtab = off;
@@ -406,6 +429,7 @@ lbm_status lbm_grid_bind(lbm_grid *g, void *ws, size_t bytes, void *stream) {
     up(r.off_bbm, r.L->bbm.data(), r.L->bbm.size() * 8);
     up(r.off_coords, r.packed.data(), r.packed.size() * 4);
     up(r.off_canon, r.L->canon.data(), r.L->canon.size() * 4);
+    up(r.off_fmask, r.L->fmask.data(), r.L->fmask.size() * 8);
     if (r.M) {
       up(r.off_jtab, r.M->jtab.data(), r.M->jtab.size() * 4);
       up(r.off_jlist, r.M->jlist.data(), r.M->jlist.size() * 4);
@@ -568,6 +592,212 @@ lbm_status lbm_get_index_map(const lbm_grid *g, int32_t level, lbm_map which, vo
     default: return fail(LBM_ERR_INVALID_ARG, "unknown map");
   }
   *count = n;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------ learned closure --
+
+lbm_status lbm_mlp_create(lbm_mlp **out, size_t *bytes) {
+  if (!out || !bytes) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  lbm_mlp *m = new (std::nothrow) lbm_mlp;
+  if (!m) return fail(LBM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  const int64_t bmax = LBM_MLP_BATCH_MAX;
+  size_t off = 0;
+  auto take = [&](size_t &o, size_t n) {
+    o = off;
+    off = align256(off + n);
+  };
+  take(m->off_params, kMlpParams * 4);
+  take(m->off_m, kMlpParams * 4);
+  take(m->off_v, kMlpParams * 4);
+  take(m->off_grads, kMlpParams * 4);
+  take(m->off_w, kWPackedElems * 2);
+  take(m->off_bias, kBiasFloats * 4);
+  take(m->off_stdz, kStdFloats * 4);
+  take(m->off_fb, 256);
+  take(m->off_save, (size_t)bmax * kSaveFloats * 4);
+  take(m->off_dyt, (size_t)bmax * Q * 4);
+  take(m->off_dz1, (size_t)bmax * 64 * 4);
+  take(m->off_dz2, (size_t)bmax * 64 * 4);
+  take(m->off_partial, 8192 * 8);
+  take(m->off_loss, 64);
+  m->total = off;
+  m->B.batch_max = bmax;
+  *out = m;
+  *bytes = m->total;
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_bind(lbm_mlp *m, void *dev, size_t bytes, void *stream) {
+  if (!m || !dev) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (m->ws) return fail(LBM_ERR_STATE, "closure already bound");
+  if (bytes < m->total) return fail(LBM_ERR_INVALID_ARG, "buffer too small (%zu < %zu)", bytes, m->total);
+  if (((uintptr_t)dev) & 255) return fail(LBM_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
+  m->ws = (char *)dev;
+  MlpBuffers &B = m->B;
+  B.params = (float *)(m->ws + m->off_params);
+  B.adam_m = (float *)(m->ws + m->off_m);
+  B.adam_v = (float *)(m->ws + m->off_v);
+  B.grads = (float *)(m->ws + m->off_grads);
+  B.wpacked = m->ws + m->off_w;
+  B.bias = (float *)(m->ws + m->off_bias);
+  B.stdz = (float *)(m->ws + m->off_stdz);
+  B.fallbacks = (unsigned int *)(m->ws + m->off_fb);
+  B.save = (float *)(m->ws + m->off_save);
+  B.dyt = (float *)(m->ws + m->off_dyt);
+  B.dz1 = (float *)(m->ws + m->off_dz1);
+  B.dz2 = (float *)(m->ws + m->off_dz2);
+  B.partial = (double *)(m->ws + m->off_partial);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<float> zeros(kMlpParams, 0.0f), stdz(kStdFloats, 0.0f);
+  for (int i = 0; i < 32; ++i) {
+    stdz[32 + i] = 1.0f;
+    stdz[64 + i] = 1.0f;
+  }
+  const uint32_t zero_count[64] = {0};
+  hipError_t e = hipMemcpyAsync(B.params, zeros.data(), kMlpParams * 4, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(B.adam_m, zeros.data(), kMlpParams * 4, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(B.adam_v, zeros.data(), kMlpParams * 4, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(B.stdz, stdz.data(), kStdFloats * 4, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(B.fallbacks, zero_count, sizeof zero_count, hipMemcpyHostToDevice, s);
+  if (!e) e = mlp_pack(B, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "mlp_bind");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_set_params(lbm_mlp *m, const float *host, void *stream) {
+  if (!m || !host) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(m->B.params, host, kMlpParams * 4, hipMemcpyHostToDevice, s);
+  if (!e) e = mlp_pack(m->B, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "mlp_set_params");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_get_params(lbm_mlp *m, float *host, void *stream) {
+  if (!m || !host) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(host, m->B.params, kMlpParams * 4, hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "mlp_get_params");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_set_standardization(lbm_mlp *m, const float *host, void *stream) {
+  if (!m || !host) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(m->B.stdz, host, kStdFloats * 4, hipMemcpyHostToDevice, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "mlp_set_standardization");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_get_standardization(lbm_mlp *m, float *host, void *stream) {
+  if (!m || !host) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(host, m->B.stdz, kStdFloats * 4, hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "mlp_get_standardization");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_fit_standardization(lbm_mlp *m, const float *f, int64_t n, void *stream) {
+  if (!m || !f || n <= 0) return fail(LBM_ERR_INVALID_ARG, "bad argument");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipError_t e = mlp_fit_standardization(m->B, f, n, (hipStream_t)stream);
+  if (e) return hip_fail(e, "mlp_fit_standardization");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_forward(lbm_mlp *m, const float *f, int64_t n, float *y, void *stream) {
+  if (!m || !f || !y || n < 0) return fail(LBM_ERR_INVALID_ARG, "bad argument");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipError_t e = mlp_forward(m->B, f, n, y, (hipStream_t)stream);
+  if (e) return hip_fail(e, "mlp_forward");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_gradients(lbm_mlp *m, const float *f, int64_t n, float *grads, double *loss, void *stream) {
+  if (!m || !f) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (n <= 0 || n > LBM_MLP_BATCH_MAX) return fail(LBM_ERR_INVALID_ARG, "batch size must be 1..%d", LBM_MLP_BATCH_MAX);
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = mlp_gradients(m->B, f, n, loss, s);
+  if (!e && grads) e = hipMemcpyAsync(grads, m->B.grads, kMlpParams * 4, hipMemcpyDeviceToDevice, s);
+  if (e) return hip_fail(e, "mlp_gradients");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f, int64_t n, float lr, int32_t t, double *loss,
+                              void *stream) {
+  if (!m || !f) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (n <= 0 || n > LBM_MLP_BATCH_MAX) return fail(LBM_ERR_INVALID_ARG, "batch size must be 1..%d", LBM_MLP_BATCH_MAX);
+  if (t < 1 || !(lr > 0)) return fail(LBM_ERR_INVALID_ARG, "need t >= 1 and lr > 0");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = mlp_gradients(m->B, f, n, loss, s);
+  if (!e) e = mlp_adam(m->B, lr, t, s);
+  if (e) return hip_fail(e, "mlp_train_step");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_fallbacks(lbm_mlp *m, uint64_t *count, int32_t reset, void *stream) {
+  if (!m || !count) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t c = 0;
+  hipError_t e = hipMemcpyAsync(&c, m->B.fallbacks, 4, hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (!e && reset) {
+    const uint32_t z = 0;
+    e = hipMemcpyAsync(m->B.fallbacks, &z, 4, hipMemcpyHostToDevice, s);
+    if (!e) e = hipStreamSynchronize(s);
+  }
+  if (e) return hip_fail(e, "mlp_fallbacks");
+  *count = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_destroy(lbm_mlp *m) {
+  delete m;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_collision(lbm_grid *g, lbm_collision c, const lbm_mlp *m) {
+  if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
+  if (c < LBM_BGK || c > LBM_MLP) return fail(LBM_ERR_INVALID_ARG, "unknown collision");
+  if (c == LBM_MLP) {
+    if (!m || !m->ws) return fail(LBM_ERR_INVALID_ARG, "LBM_MLP needs a bound closure");
+    if (g->lex || g->desc.kind == LBM_MULTIRES || g->desc.schedule != LBM_DISAGG)
+      return fail(LBM_ERR_UNSUPPORTED, "the closure runs on dense or block-sparse grids in the disaggregated schedule");
+    g->mlp = m;
+  }
+  g->collision = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_sample_populations(lbm_grid *g, int32_t level, uint64_t seed, int64_t n, float *f, void *stream) {
+  if (!g || !f || n < 0) return fail(LBM_ERR_INVALID_ARG, "bad argument");
+  if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
+  if (lbm_status st = check_level(g, level)) return st;
+  const LevelRT &r = g->lv[level];
+  int64_t slot0 = 0, nslots = r.S;
+  if (r.L) {
+    const auto &gc = r.L->group_count;
+    slot0 = (gc[0] + gc[1]) * 64;
+    nslots = (gc[2] + gc[3]) * 64;
+  }
+  if (nslots <= 0) return fail(LBM_ERR_INVALID_ARG, "the level has no non-boundary blocks");
+  hipError_t e = sample_slots(pop_ptr(g, r, r.cur), (uint32_t)r.S, g->desc.storage,
+                              r.L ? (const int32_t *)(g->ws + r.off_canon) : nullptr, slot0, nslots, seed, n, f,
+                              (hipStream_t)stream);
+  if (e) return hip_fail(e, "sample_populations");
   return LBM_OK;
 }
 

@@ -26,6 +26,12 @@ struct StepArgs {
   int32_t nx, ny, nz;        // box in voxels
   float omega;               // 1 / tau
   FaceParams fp;
+  const uint64_t *fmask;     // [nblocks] fluid voxels of each block
+  // learned closure (interior groups when the collision is LBM_MLP)
+  const void *mlp_w;              // packed bf16 weights
+  const float *mlp_bias;          // b1 | b2 | b3
+  const float *mlp_stdz;          // in_mean | in_inv_std | out_std | out_mean (32 each)
+  unsigned int *mlp_fallbacks;    // voxels that fell back to the regularized operator
 };
 
 enum KernelKind : int32_t {
@@ -57,6 +63,32 @@ struct Launch {
 };
 
 hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipStream_t s);
+
+// ---- learned closure: training and utility launches (mlp_kernels.hip) ----
+struct MlpBuffers {
+  float *params;      // [kMlpParams] FP32 master weights
+  float *adam_m;      // [kMlpParams]
+  float *adam_v;      // [kMlpParams]
+  float *grads;       // [kMlpParams]
+  void *wpacked;      // packed bf16 weights
+  float *bias;        // b1 | b2 | b3 (padded)
+  float *stdz;        // standardization, 4 x 32
+  unsigned int *fallbacks;
+  float *save;        // [batch_max][288] forward intermediates
+  float *dyt;         // [batch_max][19]
+  float *dz1;         // [batch_max][64]
+  float *dz2;         // [batch_max][64]
+  double *partial;    // reduction partials
+  int64_t batch_max;
+};
+
+hipError_t mlp_pack(const MlpBuffers &B, hipStream_t s);
+hipError_t mlp_fit_standardization(const MlpBuffers &B, const float *f, int64_t n, hipStream_t s);
+hipError_t mlp_forward(const MlpBuffers &B, const float *f, int64_t n, float *y, hipStream_t s);
+hipError_t mlp_gradients(const MlpBuffers &B, const float *f, int64_t n, double *loss, hipStream_t s);
+hipError_t mlp_adam(const MlpBuffers &B, float lr, int32_t t, hipStream_t s);
+hipError_t sample_slots(const void *pop, uint32_t S, int32_t storage, const int32_t *canon, int64_t slot0,
+                        int64_t nslots, uint64_t seed, int64_t n, float *out, hipStream_t s);
 
 // Utility kernels over a slot range [0, nslots) with an optional canonical
 // map (NULL = identity, every slot fluid).

@@ -25,6 +25,7 @@
 
 #include "device_common.h"
 #include "launch.h"
+#include "mlp_device.h"
 
 namespace lbm {
 
@@ -94,6 +95,88 @@ __global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, 
 
   if constexpr (FUSED) collide<COLL>(h, a.omega);
 
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+}
+
+// ------------------------------------------ interior kernel, learned closure --
+// Same gather as k_block_interior; the collision evaluates the closure
+// network for the wave's 64 voxels on the matrix cores, projects its output
+// to zero mass and momentum, and falls back per voxel to the regularized
+// operator when a standardized input leaves [-8, 8] or a population turns
+// negative.  The packed weights are staged in LDS once per workgroup.
+template <class ST, bool MASKED>
+__global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t g0, int32_t n) {
+  using T = typename ST::T;
+  __shared__ __attribute__((aligned(16))) __bf16 wl[kWPackedElems];
+  __shared__ __attribute__((aligned(16))) __bf16 act[4][64 * kActStride];
+  stage_weights(wl, (const __bf16 *)a.mlp_w);
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wave = threadIdx.x >> 6;
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + wave);
+  if (b >= g0 + n) return;
+  const int lane = threadIdx.x & 63;
+  const T *__restrict__ src = (const T *)a.src;
+  T *__restrict__ dst = (T *)a.dst;
+  const uint32_t S = a.S;
+  const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
+  int32_t nbv[18];
+#pragma unroll
+  for (int d = 0; d < 18; ++d) nbv[d] = a.nbr[(size_t)b * 18 + d];
+  uint64_t bm[18];
+  if constexpr (MASKED) {
+#pragma unroll
+    for (int d = 0; d < 18; ++d) bm[d] = a.bbm[(size_t)b * 18 + d];
+  }
+  float h[Q];
+  h[0] = ST::load(src, own_slot);
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    uint32_t slot = pull_slot<i>(lane, b, nbv);
+    uint32_t plane = i;
+    if constexpr (MASKED) {
+      if ((bm[i - 1] >> lane) & 1ull) {
+        slot = own_slot;
+        plane = kOpp[i];
+      }
+    }
+    h[i] = ST::load(src + (size_t)plane * S, slot);
+  });
+  const bool fluid = MASKED ? ((a.fmask[b] >> lane) & 1ull) != 0 : true;
+
+  // closure inputs g = f/rho - w, standardized
+  const Moments m = moments(h);
+  const float *sd = a.mlp_stdz;
+  const float ir = 1.0f / m.rho;
+  float x[Q];
+  bool out_of_range = false;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float g = (h[i] - weight_f(i) * m.drho) * ir;
+    x[i] = fluid ? (g - sd[i]) * sd[32 + i] : 0.0f;
+    out_of_range = out_of_range || fabsf(x[i]) > 8.0f;
+  }
+  float y[Q];
+  mlp_forward_wave(x, y, act[wave], wl, a.mlp_bias, lane);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) y[i] = fmaf(y[i], sd[64 + i], sd[96 + i]);
+  project_out(y);
+  float heq[Q], hs[Q];
+  equilibrium(m, heq);
+  const float r = (1.0f - a.omega) * m.rho;
+  bool negative = false;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    hs[i] = fmaf(r, y[i], heq[i]);
+    negative = negative || (weight_f(i) + hs[i] < 0.0f);
+  }
+  const bool fb = fluid && (out_of_range || negative);
+  if (fb) collide_regularized_m(h, m, a.omega);
+  else
+#pragma unroll
+    for (int i = 0; i < Q; ++i) h[i] = hs[i];
+  const uint64_t bal = __ballot(fb);
+  if (lane == 0 && bal) atomicAdd(a.mlp_fallbacks, (unsigned int)__popcll(bal));
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
 }
@@ -337,7 +420,30 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class ST>
+static hipError_t launch_mlp(const Launch &L, hipStream_t s) {
+  const int32_t g0 = L.first, n = L.count;
+  if (n <= 0) return hipSuccess;
+  const dim3 grd((n + 3) / 4), blk(256);
+  if (L.kind == kKernelFull) hipLaunchKernelGGL((k_block_interior_mlp<ST, false>), grd, blk, 0, s, L.args, g0, n);
+  else hipLaunchKernelGGL((k_block_interior_mlp<ST, true>), grd, blk, 0, s, L.args, g0, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipStream_t s) {
+  if (collision == kCollMLP) {
+    // the closure runs on the non-boundary groups; every other kernel uses
+    // the regularized operator it was trained to imitate
+    if (L.fused && (L.kind == kKernelFull || L.kind == kKernelMasked)) {
+      switch (storage) {
+        case LBM_F32: return launch_mlp<StoreF32>(L, s);
+        case LBM_F16_SHIFTED: return launch_mlp<StoreF16>(L, s);
+        case LBM_BF16_SHIFTED: return launch_mlp<StoreBF16>(L, s);
+      }
+      return hipErrorInvalidValue;
+    }
+    collision = kCollRegularized;
+  }
   const bool reg = collision == kCollRegularized;
   switch (storage) {
     case LBM_F32: return reg ? launch_t<StoreF32, kCollRegularized>(L, s) : launch_t<StoreF32, kCollBGK>(L, s);

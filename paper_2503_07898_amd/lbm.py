@@ -77,6 +77,20 @@ def lib() -> ctypes.CDLL:
             "lbm_get_index_map": ([vp, i32, i32, vp, ctypes.POINTER(sz)], i32),
             "lbm_step_launches": ([vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)], i32),
             "lbm_launch_group": ([vp, i32, vp], i32),
+            "lbm_mlp_create": ([ctypes.POINTER(vp), ctypes.POINTER(sz)], i32),
+            "lbm_mlp_bind": ([vp, vp, sz, vp], i32),
+            "lbm_mlp_set_params": ([vp, vp, vp], i32),
+            "lbm_mlp_get_params": ([vp, vp, vp], i32),
+            "lbm_mlp_set_standardization": ([vp, vp, vp], i32),
+            "lbm_mlp_get_standardization": ([vp, vp, vp], i32),
+            "lbm_mlp_fit_standardization": ([vp, vp, i64, vp], i32),
+            "lbm_mlp_forward": ([vp, vp, i64, vp, vp], i32),
+            "lbm_mlp_gradients": ([vp, vp, i64, vp, vp, vp], i32),
+            "lbm_mlp_train_step": ([vp, vp, i64, ctypes.c_float, i32, vp, vp], i32),
+            "lbm_mlp_fallbacks": ([vp, ctypes.POINTER(ctypes.c_uint64), i32, vp], i32),
+            "lbm_mlp_destroy": ([vp], i32),
+            "lbm_set_collision": ([vp, i32, vp], i32),
+            "lbm_sample_populations": ([vp, i32, ctypes.c_uint64, i64, vp, vp], i32),
             "lbm_grid_destroy": ([vp], i32),
         }
         for name, (args, res) in sigs.items():
@@ -173,6 +187,79 @@ def lbm_step_launches(g) -> list[int]:
 
 def lbm_launch_group(g, k: int, stream=None) -> None:
     check(lib().lbm_launch_group(g, int(k), _stream_ptr(stream)))
+
+
+MLP_PARAMS = 6675
+MLP_BATCH_MAX = 8192
+
+
+def lbm_mlp_create():
+    h = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    check(lib().lbm_mlp_create(ctypes.byref(h), ctypes.byref(n)))
+    return h, n.value
+
+
+def lbm_mlp_bind(m, ptr: int, nbytes: int, stream=None) -> None:
+    check(lib().lbm_mlp_bind(m, ctypes.c_void_p(ptr), nbytes, _stream_ptr(stream)))
+
+
+def lbm_mlp_set_params(m, params: np.ndarray, stream=None) -> None:
+    p = np.ascontiguousarray(params, np.float32)
+    assert p.size == MLP_PARAMS
+    check(lib().lbm_mlp_set_params(m, p.ctypes.data, _stream_ptr(stream)))
+
+
+def lbm_mlp_get_params(m, stream=None) -> np.ndarray:
+    p = np.zeros(MLP_PARAMS, np.float32)
+    check(lib().lbm_mlp_get_params(m, p.ctypes.data, _stream_ptr(stream)))
+    return p
+
+
+def lbm_mlp_set_standardization(m, stdz: np.ndarray, stream=None) -> None:
+    p = np.ascontiguousarray(stdz, np.float32)
+    assert p.size == 128
+    check(lib().lbm_mlp_set_standardization(m, p.ctypes.data, _stream_ptr(stream)))
+
+
+def lbm_mlp_get_standardization(m, stream=None) -> np.ndarray:
+    p = np.zeros(128, np.float32)
+    check(lib().lbm_mlp_get_standardization(m, p.ctypes.data, _stream_ptr(stream)))
+    return p
+
+
+def lbm_mlp_fit_standardization(m, f_ptr: int, n: int, stream=None) -> None:
+    check(lib().lbm_mlp_fit_standardization(m, f_ptr, int(n), _stream_ptr(stream)))
+
+
+def lbm_mlp_forward(m, f_ptr: int, n: int, y_ptr: int, stream=None) -> None:
+    check(lib().lbm_mlp_forward(m, f_ptr, int(n), y_ptr, _stream_ptr(stream)))
+
+
+def lbm_mlp_gradients(m, f_ptr: int, n: int, grads_ptr, loss_ptr, stream=None) -> None:
+    check(lib().lbm_mlp_gradients(m, f_ptr, int(n), grads_ptr, loss_ptr, _stream_ptr(stream)))
+
+
+def lbm_mlp_train_step(m, f_ptr: int, n: int, lr: float, t: int, loss_ptr=None, stream=None) -> None:
+    check(lib().lbm_mlp_train_step(m, f_ptr, int(n), float(lr), int(t), loss_ptr, _stream_ptr(stream)))
+
+
+def lbm_mlp_fallbacks(m, reset: bool = False, stream=None) -> int:
+    c = ctypes.c_uint64()
+    check(lib().lbm_mlp_fallbacks(m, ctypes.byref(c), 1 if reset else 0, _stream_ptr(stream)))
+    return c.value
+
+
+def lbm_mlp_destroy(m) -> None:
+    check(lib().lbm_mlp_destroy(m))
+
+
+def lbm_set_collision(g, collision: int, mlp=None) -> None:
+    check(lib().lbm_set_collision(g, int(collision), mlp))
+
+
+def lbm_sample_populations(g, level: int, seed: int, n: int, f_ptr: int, stream=None) -> None:
+    check(lib().lbm_sample_populations(g, int(level), ctypes.c_uint64(seed), int(n), f_ptr, _stream_ptr(stream)))
 
 
 def lbm_grid_destroy(g) -> None:
@@ -289,6 +376,16 @@ class Grid:
     def launches(self) -> list[int]:
         return lbm_step_launches(self.h)
 
+    def set_collision(self, collision: int, mlp=None) -> None:
+        self._mlp_keep = mlp
+        lbm_set_collision(self.h, collision, None if mlp is None else mlp.h)
+
+    def sample(self, seed: int, n: int, level: int = 0):
+        import torch
+        f = torch.empty(n, 19, dtype=torch.float32, device=self.device)
+        lbm_sample_populations(self.h, level, seed, n, f.data_ptr())
+        return f
+
     def close(self):
         if getattr(self, "h", None) is not None:
             lbm_grid_destroy(self.h)
@@ -299,3 +396,75 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+class Mlp:
+    """The learned collision closure with its device buffer (torch tensor)."""
+
+    def __init__(self, device: str = "cuda"):
+        import torch
+        self.h, self.nbytes = lbm_mlp_create()
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.device = device
+        lbm_mlp_bind(self.h, self.buf.data_ptr(), self.nbytes)
+
+    def set_params(self, params) -> None:
+        lbm_mlp_set_params(self.h, np.asarray(params, np.float32).reshape(-1))
+
+    def params(self) -> np.ndarray:
+        return lbm_mlp_get_params(self.h)
+
+    def set_standardization(self, stdz) -> None:
+        lbm_mlp_set_standardization(self.h, np.asarray(stdz, np.float32).reshape(-1))
+
+    def standardization(self) -> np.ndarray:
+        return lbm_mlp_get_standardization(self.h)
+
+    def fit_standardization(self, f) -> None:
+        lbm_mlp_fit_standardization(self.h, f.data_ptr(), f.shape[0])
+
+    def forward(self, f):
+        import torch
+        y = torch.empty(f.shape[0], 19, dtype=torch.float32, device=self.device)
+        lbm_mlp_forward(self.h, f.data_ptr(), f.shape[0], y.data_ptr())
+        return y
+
+    def gradients(self, f):
+        import torch
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        lbm_mlp_gradients(self.h, f.data_ptr(), f.shape[0], g.data_ptr(), loss.data_ptr())
+        return g, loss
+
+    def train_step(self, f, lr: float, t: int, loss=None) -> None:
+        lbm_mlp_train_step(self.h, f.data_ptr(), f.shape[0], lr, t, None if loss is None else loss.data_ptr())
+
+    def fallbacks(self, reset: bool = False) -> int:
+        return lbm_mlp_fallbacks(self.h, reset)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lbm_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def flatten_params(W) -> np.ndarray:
+    """[W1 (19,64), b1, W2 (64,64), b2, W3 (64,19), b3] -> flat LBM_MLP_PARAMS array."""
+    return np.concatenate([np.asarray(w, np.float64).reshape(-1) for w in W]).astype(np.float32)
+
+
+def unflatten_params(p) -> list:
+    p = np.asarray(p, np.float64)
+    shapes = [(19, 64), (64,), (64, 64), (64,), (64, 19), (19,)]
+    out, k = [], 0
+    for s in shapes:
+        n = int(np.prod(s))
+        out.append(p[k:k + n].reshape(s))
+        k += n
+    return out
