@@ -207,13 +207,15 @@ lbm_status lbm_step_launches(const lbm_grid *g, int64_t *blocks_out, int32_t max
 /* ------------------------------------------------- learned collision closure
  * A 19-64-64-19 perceptron with tanh-form GELU activations (an addition of
  * this library; the paper has no learned component).  Input: the
- * standardized non-equilibrium state g = f/rho - w of a voxel; output: an
+ * standardized non-equilibrium part per unit density of a voxel,
+ * g = (f - f^eq(rho, u))/rho; output: an
  * estimate y of the regularized operator's non-equilibrium part per unit
  * density, projected to zero mass and momentum, P(y); post-collision state
  * f* = f^eq + (1 - 1/tau) rho P(y).  Inference and training forward run on
  * the matrix cores in bfloat16 with FP32 accumulation; FP32 master weights
  * are trained with Adam (beta 0.9 / 0.999, eps 1e-8) on the mean squared
- * error of P(y) against f1/rho.  Parameters are flat FP32 arrays of
+ * error of P(y) against f1/rho divided by the mean target variance (a
+ * scale-free loss; the raw error is of order 1e-9).  Parameters are flat FP32 arrays of
  * LBM_MLP_PARAMS values: W1 [19][64], b1 [64], W2 [64][64], b2 [64],
  * W3 [64][19], b3 [19] (row-major, W_k indexed [input][output]).
  * Standardization: 128 floats, in_mean [32] | in_inv_std [32] |
@@ -238,13 +240,16 @@ lbm_status lbm_mlp_get_standardization(lbm_mlp *m, float *host_stdz, void *strea
 lbm_status lbm_mlp_fit_standardization(lbm_mlp *m, const float *f_dev, int64_t n, void *stream);
 /* Network output y (de-standardized, before projection) for n populations. */
 lbm_status lbm_mlp_forward(lbm_mlp *m, const float *f_dev, int64_t n, float *y_dev, void *stream);
-/* Loss and gradients of one batch (n <= LBM_MLP_BATCH_MAX): grads_dev
- * [LBM_MLP_PARAMS] (may be NULL), loss_dev one double (may be NULL). */
-lbm_status lbm_mlp_gradients(lbm_mlp *m, const float *f_dev, int64_t n, float *grads_dev,
-                             double *loss_dev, void *stream);
-/* One training step: gradients of the batch, then Adam step t (t >= 1). */
-lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f_dev, int64_t n, float lr, int32_t t,
-                              double *loss_dev, void *stream);
+/* Loss and gradients of one batch of n <= LBM_MLP_BATCH_MAX populations:
+ * rows idx_dev[0..n) of f_dev (int64 device array), or rows 0..n-1 when
+ * idx_dev is NULL.  grads_dev [LBM_MLP_PARAMS] and loss_dev (one double)
+ * may be NULL. */
+lbm_status lbm_mlp_gradients(lbm_mlp *m, const float *f_dev, const int64_t *idx_dev, int64_t n,
+                             float *grads_dev, double *loss_dev, void *stream);
+/* One training step on such a batch: gradients, then Adam step t (t >= 1)
+ * with learning rate lr on the FP32 master weights, then the bf16 copy. */
+lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f_dev, const int64_t *idx_dev, int64_t n,
+                              float lr, int32_t t, double *loss_dev, void *stream);
 /* Voxels that fell back to the regularized operator since bind/reset. */
 lbm_status lbm_mlp_fallbacks(lbm_mlp *m, uint64_t *host_count, int32_t reset, void *stream);
 lbm_status lbm_mlp_destroy(lbm_mlp *m);
@@ -255,9 +260,12 @@ lbm_status lbm_mlp_destroy(lbm_mlp *m);
  * regularized operator.  The closure must outlive its use by the grid. */
 lbm_status lbm_set_collision(lbm_grid *g, lbm_collision c, const lbm_mlp *m);
 
-/* n populations (FP32, unshifted, [n][19]) of fluid voxels drawn uniformly
- * (with replacement, counter-based splitmix64 stream from `seed`) from the
- * non-boundary groups of `level` -- the training data of the closure. */
+/* n pre-collision population sets (FP32, unshifted, [n][19]: the values the
+ * collision operator of the next step receives, pulled from the current
+ * post-collision field with bounce-back) of fluid voxels drawn uniformly
+ * with replacement from the non-boundary groups of `level` (counter-based
+ * splitmix64 stream from `seed`) -- the training data of the closure.
+ * Needs a block layout. */
 lbm_status lbm_sample_populations(lbm_grid *g, int32_t level, uint64_t seed, int64_t n, float *f_dev,
                                   void *stream);
 

@@ -5,9 +5,10 @@ module; it shares no code with the GPU library.
 
 The closure (an addition of this build; nothing in the paper): a
 19 -> 64 -> 64 -> 19 perceptron with tanh-form GELU activations maps the
-standardized non-equilibrium state of a voxel, g = f/rho - w, to an
-estimate y of the regularized non-equilibrium part per unit density,
-f1/rho (the Hermite projection of the regularized collision).  The
+standardized non-equilibrium part of a voxel per unit density,
+g = (f - f^eq(rho, u)) / rho, to an estimate y of the regularized
+non-equilibrium part per unit density, f1/rho (the Hermite projection of
+the regularized collision).  The
 estimate is projected so that it carries no mass and no momentum,
 
     P(y)_i = y_i - w_i sum_j y_j - w_i c_i . (sum_j c_j y_j) / c_s^2,
@@ -15,7 +16,8 @@ estimate is projected so that it carries no mass and no momentum,
 and the post-collision state is f* = f^eq + (1 - 1/tau) rho P(y).  A voxel
 falls back to the regularized operator if any standardized input exceeds 8
 in magnitude or any output population is negative.  Training minimizes the
-mean squared error between P(y) and f1/rho with Adam.
+mean squared error between P(y) and f1/rho, divided by the mean target
+variance (mean of out_std^2) so that the loss is scale free, with Adam.
 """
 from __future__ import annotations
 
@@ -115,14 +117,14 @@ def forward(p: Params, g, cache: bool = False):
 
 def loss(p: Params, g, target):
     d = project(forward(p, g)) - target
-    return float(np.mean(d * d))
+    return float(np.mean(d * d) / np.mean(p.out_std ** 2))
 
 
 def backward(p: Params, g, target):
     """Gradients of loss() with respect to W1, b1, W2, b2, W3, b3."""
     y, (x, z1, h1, z2, h2) = forward(p, g, cache=True)
     n = y.shape[0]
-    dP = 2.0 * (project(y) - target) / (n * Q)
+    dP = 2.0 * (project(y) - target) / (n * Q * np.mean(p.out_std ** 2))
     dy = dP @ projection_matrix()
     dyt = dy * p.out_std
     gW3 = h2.T @ dyt
@@ -165,10 +167,13 @@ def regularized_target(f):
 
 
 def closure_inputs(f):
-    """g = f/rho - w for populations f (N, 19)."""
-    _, w = lattice()
-    f = np.asarray(f, np.float64)
-    return f / f.sum(-1, keepdims=True) - w
+    """g = (f - f^eq(rho, u)) / rho for populations f (N, 19)."""
+    f = np.asarray(f, np.float64).reshape(-1, Q)
+    out = np.zeros_like(f)
+    for k in range(f.shape[0]):
+        rho, u = _orc.moments(f[k])
+        out[k] = (f[k] - _orc.equilibrium(rho, u)) / rho
+    return out
 
 
 def collide(p: Params, f, tau, y_override=None):

@@ -723,25 +723,26 @@ lbm_status lbm_mlp_forward(lbm_mlp *m, const float *f, int64_t n, float *y, void
   return LBM_OK;
 }
 
-lbm_status lbm_mlp_gradients(lbm_mlp *m, const float *f, int64_t n, float *grads, double *loss, void *stream) {
+lbm_status lbm_mlp_gradients(lbm_mlp *m, const float *f, const int64_t *idx, int64_t n, float *grads, double *loss,
+                             void *stream) {
   if (!m || !f) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (n <= 0 || n > LBM_MLP_BATCH_MAX) return fail(LBM_ERR_INVALID_ARG, "batch size must be 1..%d", LBM_MLP_BATCH_MAX);
   if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = mlp_gradients(m->B, f, n, loss, s);
+  hipError_t e = mlp_gradients(m->B, f, idx, n, loss, s);
   if (!e && grads) e = hipMemcpyAsync(grads, m->B.grads, kMlpParams * 4, hipMemcpyDeviceToDevice, s);
   if (e) return hip_fail(e, "mlp_gradients");
   return LBM_OK;
 }
 
-lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f, int64_t n, float lr, int32_t t, double *loss,
-                              void *stream) {
+lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f, const int64_t *idx, int64_t n, float lr, int32_t t,
+                              double *loss, void *stream) {
   if (!m || !f) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (n <= 0 || n > LBM_MLP_BATCH_MAX) return fail(LBM_ERR_INVALID_ARG, "batch size must be 1..%d", LBM_MLP_BATCH_MAX);
   if (t < 1 || !(lr > 0)) return fail(LBM_ERR_INVALID_ARG, "need t >= 1 and lr > 0");
   if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = mlp_gradients(m->B, f, n, loss, s);
+  hipError_t e = mlp_gradients(m->B, f, idx, n, loss, s);
   if (!e) e = mlp_adam(m->B, lr, t, s);
   if (e) return hip_fail(e, "mlp_train_step");
   return LBM_OK;
@@ -787,16 +788,13 @@ lbm_status lbm_sample_populations(lbm_grid *g, int32_t level, uint64_t seed, int
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
   if (lbm_status st = check_level(g, level)) return st;
   const LevelRT &r = g->lv[level];
-  int64_t slot0 = 0, nslots = r.S;
-  if (r.L) {
-    const auto &gc = r.L->group_count;
-    slot0 = (gc[0] + gc[1]) * 64;
-    nslots = (gc[2] + gc[3]) * 64;
-  }
-  if (nslots <= 0) return fail(LBM_ERR_INVALID_ARG, "the level has no non-boundary blocks");
-  hipError_t e = sample_slots(pop_ptr(g, r, r.cur), (uint32_t)r.S, g->desc.storage,
-                              r.L ? (const int32_t *)(g->ws + r.off_canon) : nullptr, slot0, nslots, seed, n, f,
-                              (hipStream_t)stream);
+  if (!r.L) return fail(LBM_ERR_UNSUPPORTED, "sampling needs a block layout");
+  const auto &gc = r.L->group_count;
+  const int32_t b0 = (int32_t)(gc[0] + gc[1]), nb = (int32_t)(gc[2] + gc[3]);
+  if (nb <= 0) return fail(LBM_ERR_INVALID_ARG, "the level has no non-boundary blocks");
+  StepArgs a = level_args(g, r);
+  a.src = pop_ptr(g, r, r.cur);
+  hipError_t e = launch_sample_pre(a, g->desc.storage, b0, nb, seed, n, f, (hipStream_t)stream);
   if (e) return hip_fail(e, "sample_populations");
   return LBM_OK;
 }

@@ -85,10 +85,11 @@ struct MlpBuffers {
 hipError_t mlp_pack(const MlpBuffers &B, hipStream_t s);
 hipError_t mlp_fit_standardization(const MlpBuffers &B, const float *f, int64_t n, hipStream_t s);
 hipError_t mlp_forward(const MlpBuffers &B, const float *f, int64_t n, float *y, hipStream_t s);
-hipError_t mlp_gradients(const MlpBuffers &B, const float *f, int64_t n, double *loss, hipStream_t s);
+hipError_t mlp_gradients(const MlpBuffers &B, const float *f, const int64_t *idx, int64_t n, double *loss,
+                         hipStream_t s);
 hipError_t mlp_adam(const MlpBuffers &B, float lr, int32_t t, hipStream_t s);
-hipError_t sample_slots(const void *pop, uint32_t S, int32_t storage, const int32_t *canon, int64_t slot0,
-                        int64_t nslots, uint64_t seed, int64_t n, float *out, hipStream_t s);
+hipError_t launch_sample_pre(const StepArgs &a, int32_t storage, int32_t b0, int32_t nb, uint64_t seed, int64_t n,
+                             float *out, hipStream_t s);
 
 // Utility kernels over a slot range [0, nslots) with an optional canonical
 // map (NULL = identity, every slot fluid).

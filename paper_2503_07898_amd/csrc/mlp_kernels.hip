@@ -1,7 +1,7 @@
 // Training and utility kernels of the learned collision closure.
 //
 // A training step on a batch of populations f [B][19]:
-//   k_mlp_fwd     per wave of 64 samples: g = f/rho - w, standardize, network
+//   k_mlp_fwd     per wave of 64 samples: g = (f - f^eq)/rho, standardize, network
 //                 forward on the matrix cores (the inference code path),
 //                 projection, squared error against the regularized target
 //                 f1/rho, and the loss gradient with respect to the raw
@@ -24,21 +24,31 @@ namespace {
 
 __device__ __forceinline__ float bf16_value(float v) { return (float)(__bf16)v; }
 
+// mean of out_std^2 (the loss normalization)
+__device__ __forceinline__ float s2_of(const float *stdz) {
+  float s2 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) s2 = fmaf(stdz[64 + i], stdz[64 + i], s2);
+  return s2 * (1.0f / Q);
+}
+
 // populations f (FP32, unshifted) of one sample -> shifted h
 __device__ __forceinline__ void load_sample(const float *f, int64_t k, float (&h)[Q]) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) h[i] = f[k * Q + i] - weight_f(i);
 }
 
-// standardized closure inputs x and the moments of h
+// standardized closure inputs x = ((f - f^eq)/rho - mean) / std and the moments
 __device__ __forceinline__ Moments closure_inputs(const float (&h)[Q], const float *stdz, float (&x)[Q],
                                                   bool &out_of_range) {
   const Moments m = moments(h);
+  float heq[Q];
+  equilibrium(m, heq);
   const float ir = 1.0f / m.rho;
   out_of_range = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float g = (h[i] - weight_f(i) * m.drho) * ir;  // f/rho - w
+    const float g = (h[i] - heq[i]) * ir;
     x[i] = (g - stdz[i]) * stdz[32 + i];
     out_of_range = out_of_range || fabsf(x[i]) > 8.0f;
   }
@@ -48,7 +58,7 @@ __device__ __forceinline__ Moments closure_inputs(const float (&h)[Q], const flo
 }  // namespace
 
 // ------------------------------------------------------------ forward/loss --
-__global__ __launch_bounds__(256) void k_mlp_fwd(const float *f, int64_t n, const __bf16 *wg,
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float *f, const int64_t *idx, int64_t n, const __bf16 *wg,
                                                  const float *bias, const float *stdz, float *save,
                                                  float *dyt, float *yout, double *partial) {
   __shared__ __attribute__((aligned(16))) __bf16 wl[kWPackedElems];
@@ -59,7 +69,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *f, int64_t n, cons
   const int64_t k = row0 + lane;
   const bool valid = k < n;
   float h[Q], x[Q], yt[Q];
-  if (valid) load_sample(f, k, h);
+  if (valid) load_sample(f, idx ? idx[k] : k, h);
   else
 #pragma unroll
     for (int i = 0; i < Q; ++i) h[i] = 0.0f;
@@ -85,8 +95,11 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *f, int64_t n, cons
     d[i] = valid ? y[i] - f1[i] * ir : 0.0f;
     e += (double)d[i] * (double)d[i];
   }
-  // dL/dP = 2 d / (n 19); dL/dy = dL/dP * M with M_ij = delta_ij - w_i - 3 w_i c_i.c_j
-  const float sc = 2.0f / (float)(n * Q);
+  e = e / (double)s2_of(stdz);
+  // loss = mean d^2 / s2 with s2 the mean target variance (scale-free loss);
+  // dL/dP = 2 d / (n 19 s2); dL/dy = dL/dP * M, M_ij = delta_ij - w_i - 3 w_i c_i.c_j
+  const float s2 = s2_of(stdz);
+  const float sc = 2.0f / ((float)(n * Q) * s2);
   float sw = 0.0f, swx = 0.0f, swy = 0.0f, swz = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -208,7 +221,7 @@ __global__ void k_mlp_pack(const float *params, __bf16 *wp, float *bias) {
 }
 
 // ------------------------------------------------------ standardization --
-// Per-component mean and standard deviation of the inputs g = f/rho - w
+// Per-component mean and standard deviation of the inputs g = (f - f^eq)/rho
 // and of the targets f1/rho, FP64 sums in a fixed order.
 __global__ __launch_bounds__(256) void k_stats_partial(const float *f, int64_t n, double *partial) {
   __shared__ double sh[256];
@@ -218,10 +231,12 @@ __global__ __launch_bounds__(256) void k_stats_partial(const float *f, int64_t n
     float h[Q], f1[Q];
     load_sample(f, s, h);
     const Moments m = moments(h);
+    float heq[Q];
+    equilibrium(m, heq);
     f1_projection(h, m, f1);
     const float ir = 1.0f / m.rho;
     for (int i = 0; i < Q; ++i) {
-      const double g = (double)((h[i] - weight_f(i) * m.drho) * ir);
+      const double g = (double)((h[i] - heq[i]) * ir);
       const double t = (double)(f1[i] * ir);
       acc[i] += g;
       acc[Q + i] += g * g;
@@ -264,34 +279,6 @@ __global__ void k_stats_final(const double *partial, int nblk, int64_t n, float 
   stdz[96 + i] = (float)mt;
 }
 
-// --------------------------------------------------------------- sampler --
-// splitmix64 (Steele, Lea and Flood 2014): a counter-based generator.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
-  x += 0x9e3779b97f4a7c15ull;
-  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
-  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
-  return x ^ (x >> 31);
-}
-
-// Draws slots uniformly from [slot0, slot0 + nslots) by rejection until a
-// fluid slot is found, and writes its populations (FP32, unshifted).
-template <class ST>
-__global__ void k_sample(const void *pop, uint32_t S, const int32_t *canon, int64_t slot0, int64_t nslots,
-                         uint64_t seed, int64_t n, float *out) {
-  using T = typename ST::T;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  int64_t slot = -1;
-  for (int attempt = 0; attempt < 4096 && slot < 0; ++attempt) {
-    const uint64_t r = splitmix64(seed ^ splitmix64((uint64_t)k * 4096u + (uint64_t)attempt));
-    const int64_t cand = slot0 + (int64_t)(r % (uint64_t)nslots);
-    if (!canon || canon[cand] >= 0) slot = cand;
-  }
-  if (slot < 0) slot = slot0;
-  const T *p = (const T *)pop;
-  for (int i = 0; i < Q; ++i) out[k * Q + i] = weight_f(i) + (float)ST::to_double(p[(size_t)i * S + slot]);
-}
-
 // ---------------------------------------------------------------- launch --
 static int64_t waves_blocks(int64_t n) { return (n + 255) / 256; }
 
@@ -309,16 +296,17 @@ hipError_t mlp_fit_standardization(const MlpBuffers &B, const float *f, int64_t 
 
 hipError_t mlp_forward(const MlpBuffers &B, const float *f, int64_t n, float *y, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)waves_blocks(n)), dim3(256), 0, s, f, n,
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)waves_blocks(n)), dim3(256), 0, s, f, (const int64_t *)nullptr, n,
                      (const __bf16 *)B.wpacked, B.bias, B.stdz, (float *)nullptr, (float *)nullptr, y,
                      (double *)nullptr);
   return hipGetLastError();
 }
 
-hipError_t mlp_gradients(const MlpBuffers &B, const float *f, int64_t n, double *loss, hipStream_t s) {
+hipError_t mlp_gradients(const MlpBuffers &B, const float *f, const int64_t *idx, int64_t n, double *loss,
+                         hipStream_t s) {
   if (n <= 0 || n > B.batch_max) return hipErrorInvalidValue;
   const unsigned nb = (unsigned)waves_blocks(n);
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(nb), dim3(256), 0, s, f, n, (const __bf16 *)B.wpacked, B.bias, B.stdz,
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(nb), dim3(256), 0, s, f, idx, n, (const __bf16 *)B.wpacked, B.bias, B.stdz,
                      B.save, B.dyt, (float *)nullptr, B.partial);
   hipLaunchKernelGGL(k_mlp_bwd, dim3(nb), dim3(256), 0, s, n, B.params, B.save, B.dyt, B.dz1, B.dz2);
   hipLaunchKernelGGL(k_mlp_wgrad, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, n, B.save, B.dyt, B.dz1,
@@ -332,19 +320,6 @@ hipError_t mlp_adam(const MlpBuffers &B, float lr, int32_t t, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, B.params, B.grads, B.adam_m,
                      B.adam_v, lr, b1c, b2c);
   return mlp_pack(B, s);
-}
-
-hipError_t sample_slots(const void *pop, uint32_t S, int32_t storage, const int32_t *canon, int64_t slot0,
-                        int64_t nslots, uint64_t seed, int64_t n, float *out, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const dim3 g((unsigned)((n + 255) / 256)), b(256);
-  switch (storage) {
-    case LBM_F32: hipLaunchKernelGGL(k_sample<StoreF32>, g, b, 0, s, pop, S, canon, slot0, nslots, seed, n, out); break;
-    case LBM_F16_SHIFTED: hipLaunchKernelGGL(k_sample<StoreF16>, g, b, 0, s, pop, S, canon, slot0, nslots, seed, n, out); break;
-    case LBM_BF16_SHIFTED: hipLaunchKernelGGL(k_sample<StoreBF16>, g, b, 0, s, pop, S, canon, slot0, nslots, seed, n, out); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
 }
 
 }  // namespace lbm

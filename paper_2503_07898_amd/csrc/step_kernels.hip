@@ -144,15 +144,17 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
   });
   const bool fluid = MASKED ? ((a.fmask[b] >> lane) & 1ull) != 0 : true;
 
-  // closure inputs g = f/rho - w, standardized
+  // closure inputs g = (f - f^eq)/rho, standardized
   const Moments m = moments(h);
+  float heq[Q];
+  equilibrium(m, heq);
   const float *sd = a.mlp_stdz;
   const float ir = 1.0f / m.rho;
   float x[Q];
   bool out_of_range = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float g = (h[i] - weight_f(i) * m.drho) * ir;
+    const float g = (h[i] - heq[i]) * ir;
     x[i] = fluid ? (g - sd[i]) * sd[32 + i] : 0.0f;
     out_of_range = out_of_range || fabsf(x[i]) > 8.0f;
   }
@@ -161,8 +163,7 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
 #pragma unroll
   for (int i = 0; i < Q; ++i) y[i] = fmaf(y[i], sd[64 + i], sd[96 + i]);
   project_out(y);
-  float heq[Q], hs[Q];
-  equilibrium(m, heq);
+  float hs[Q];
   const float r = (1.0f - a.omega) * m.rho;
   bool negative = false;
 #pragma unroll
@@ -376,6 +377,63 @@ __global__ __launch_bounds__(256) void k_lex(StepArgs a) {
 
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own, h[i]);
+}
+
+// ------------------------------------------------------ training sampler --
+// splitmix64 (Steele, Lea and Flood 2014), a counter-based generator.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+// Sample k draws block slots uniformly from [b0, b0 + nb) and lanes
+// uniformly, rejecting non-fluid voxels, and writes the pre-collision
+// populations the collision operator would see there (the pull of the
+// interior kernels, bounce-back included), unshifted FP32 [n][19].
+template <class ST>
+__global__ void k_sample_pre(StepArgs a, int32_t b0, int32_t nb, uint64_t seed, int64_t n, float *out) {
+  using T = typename ST::T;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int b = b0, lane = 0;
+  for (int attempt = 0; attempt < 4096; ++attempt) {
+    const uint64_t r = splitmix64(seed ^ splitmix64((uint64_t)k * 4096u + (uint64_t)attempt));
+    const int bb = b0 + (int)((r >> 6) % (uint64_t)nb);
+    const int ll = (int)(r & 63u);
+    b = bb;
+    lane = ll;
+    if ((a.fmask[bb] >> ll) & 1ull) break;
+  }
+  const T *src = (const T *)a.src;
+  int32_t nbv[18];
+  for (int d = 0; d < 18; ++d) nbv[d] = a.nbr[(size_t)b * 18 + d];
+  const uint32_t own = (uint32_t)b * 64u + (uint32_t)lane;
+  out[k * Q] = weight_f(0) + ST::load(src, own);
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    uint32_t slot = pull_slot<i>(lane, b, nbv);
+    uint32_t plane = i;
+    if ((a.bbm[(size_t)b * 18 + i - 1] >> lane) & 1ull) {
+      slot = own;
+      plane = kOpp[i];
+    }
+    out[k * Q + i] = weight_f(i) + ST::load(src + (size_t)plane * a.S, slot);
+  });
+}
+
+hipError_t launch_sample_pre(const StepArgs &a, int32_t storage, int32_t b0, int32_t nb, uint64_t seed, int64_t n,
+                             float *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 g((unsigned)((n + 255) / 256)), blk(256);
+  switch (storage) {
+    case LBM_F32: hipLaunchKernelGGL(k_sample_pre<StoreF32>, g, blk, 0, s, a, b0, nb, seed, n, out); break;
+    case LBM_F16_SHIFTED: hipLaunchKernelGGL(k_sample_pre<StoreF16>, g, blk, 0, s, a, b0, nb, seed, n, out); break;
+    case LBM_BF16_SHIFTED: hipLaunchKernelGGL(k_sample_pre<StoreBF16>, g, blk, 0, s, a, b0, nb, seed, n, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------- launch --

@@ -85,8 +85,8 @@ def lib() -> ctypes.CDLL:
             "lbm_mlp_get_standardization": ([vp, vp, vp], i32),
             "lbm_mlp_fit_standardization": ([vp, vp, i64, vp], i32),
             "lbm_mlp_forward": ([vp, vp, i64, vp, vp], i32),
-            "lbm_mlp_gradients": ([vp, vp, i64, vp, vp, vp], i32),
-            "lbm_mlp_train_step": ([vp, vp, i64, ctypes.c_float, i32, vp, vp], i32),
+            "lbm_mlp_gradients": ([vp, vp, vp, i64, vp, vp, vp], i32),
+            "lbm_mlp_train_step": ([vp, vp, vp, i64, ctypes.c_float, i32, vp, vp], i32),
             "lbm_mlp_fallbacks": ([vp, ctypes.POINTER(ctypes.c_uint64), i32, vp], i32),
             "lbm_mlp_destroy": ([vp], i32),
             "lbm_set_collision": ([vp, i32, vp], i32),
@@ -236,12 +236,14 @@ def lbm_mlp_forward(m, f_ptr: int, n: int, y_ptr: int, stream=None) -> None:
     check(lib().lbm_mlp_forward(m, f_ptr, int(n), y_ptr, _stream_ptr(stream)))
 
 
-def lbm_mlp_gradients(m, f_ptr: int, n: int, grads_ptr, loss_ptr, stream=None) -> None:
-    check(lib().lbm_mlp_gradients(m, f_ptr, int(n), grads_ptr, loss_ptr, _stream_ptr(stream)))
+def lbm_mlp_gradients(m, f_ptr: int, idx_ptr, n: int, grads_ptr, loss_ptr, stream=None) -> None:
+    check(lib().lbm_mlp_gradients(m, f_ptr, idx_ptr, int(n), grads_ptr, loss_ptr, _stream_ptr(stream)))
 
 
-def lbm_mlp_train_step(m, f_ptr: int, n: int, lr: float, t: int, loss_ptr=None, stream=None) -> None:
-    check(lib().lbm_mlp_train_step(m, f_ptr, int(n), float(lr), int(t), loss_ptr, _stream_ptr(stream)))
+def lbm_mlp_train_step(m, f_ptr: int, idx_ptr, n: int, lr: float, t: int, loss_ptr=None,
+                       stream=None) -> None:
+    check(lib().lbm_mlp_train_step(m, f_ptr, idx_ptr, int(n), float(lr), int(t), loss_ptr,
+                                   _stream_ptr(stream)))
 
 
 def lbm_mlp_fallbacks(m, reset: bool = False, stream=None) -> int:
@@ -433,11 +435,14 @@ class Mlp:
         import torch
         g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
         loss = torch.empty(1, dtype=torch.float64, device=self.device)
-        lbm_mlp_gradients(self.h, f.data_ptr(), f.shape[0], g.data_ptr(), loss.data_ptr())
+        lbm_mlp_gradients(self.h, f.data_ptr(), None, f.shape[0], g.data_ptr(), loss.data_ptr())
         return g, loss
 
-    def train_step(self, f, lr: float, t: int, loss=None) -> None:
-        lbm_mlp_train_step(self.h, f.data_ptr(), f.shape[0], lr, t, None if loss is None else loss.data_ptr())
+    def train_step(self, f, lr: float, t: int, loss=None, idx=None) -> None:
+        """Adam step t on rows idx (int64 device tensor) of f, or on all of f."""
+        n = f.shape[0] if idx is None else idx.shape[0]
+        lbm_mlp_train_step(self.h, f.data_ptr(), None if idx is None else idx.data_ptr(), n, lr, t,
+                           None if loss is None else loss.data_ptr())
 
     def fallbacks(self, reset: bool = False) -> int:
         return lbm_mlp_fallbacks(self.h, reset)

@@ -109,9 +109,8 @@ def train(m, data, iters, batch=4096, lr=1e-3, seed=0):
     hist = []
     for t in range(1, iters + 1):
         idx = torch.as_tensor(rng.integers(0, data.shape[0], batch), device="cuda")
-        b = data[idx].contiguous()
         lr_t = 1e-5 + 0.5 * (lr - 1e-5) * (1 + math.cos(math.pi * (t - 1) / iters))
-        m.train_step(b, lr_t, t, loss)
+        m.train_step(data, lr_t, t, loss, idx=idx)
         if t % max(1, iters // 10) == 0 or t == 1:
             hist.append(loss.item())
     return hist
