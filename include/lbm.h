@@ -86,8 +86,17 @@ typedef enum { LBM_BGK = 0, LBM_REGULARIZED = 1, LBM_MLP = 2 } lbm_collision;
  *     every boundary rule and so the boundary register demand everywhere;
  *   multires: collision and streaming as separate kernels at every level
  *     except the finest (the unfused baseline of the multires evaluation).
- * LBM_DISAGG: the disaggregated groups, one specialized kernel per group. */
-typedef enum { LBM_PLAIN_SINGLE_KERNEL = 0, LBM_DISAGG = 1 } lbm_schedule;
+ * LBM_DISAGG: the disaggregated groups, one specialized kernel per group
+ *   (memory-based grouping: each group contiguous, "Disaggregation on a
+ *   Sparse Domain", table dissBlock).
+ * LBM_DISAGG_BITMASK: the bitmask-based grouping of the same section, for
+ *   dense and block-sparse grids: blocks stay in one Morton order, a bit per
+ *   block marks the boundary blocks, and two kernels each run over every
+ *   block and skip the blocks of the other kind at run time.  Boundary
+ *   values reach the boundary kernel through indirect indexing: a 32-bit id
+ *   per voxel slot selects the voxel's entry in a contiguous buffer of
+ *   boundary-voxel records.  Not with LBM_MLP, not for sampling. */
+typedef enum { LBM_PLAIN_SINGLE_KERNEL = 0, LBM_DISAGG = 1, LBM_DISAGG_BITMASK = 2 } lbm_schedule;
 
 typedef struct {
   lbm_grid_kind kind;
@@ -187,13 +196,19 @@ lbm_status lbm_write_populations(lbm_grid *g, int32_t level, const double *f_dev
  *   LBM_MAP_NEIGHBOURS int32 [nblocks][18]: slot of the neighbour block in
  *                      direction 1..18, -1 = none
  *   LBM_MAP_FLUIDMASK  uint64 [nblocks]: bit x+4y+16z set for fluid voxels
- *   LBM_MAP_CANONICAL  int64 [nblocks*64]: canonical index of each slot, -1 = not fluid */
+ *   LBM_MAP_CANONICAL  int64 [nblocks*64]: canonical index of each slot, -1 = not fluid
+ *   LBM_MAP_BOUNDARY_BITS uint32 [(nblocks+31)/32]: bit b set if storage block b is a
+ *                      boundary-group block
+ *   LBM_MAP_RECORD_IDS int32 [nblocks*64]: bitmask layout only (else empty): boundary
+ *                      record of each slot, -1 = none */
 typedef enum {
   LBM_MAP_GROUPS = 0,
   LBM_MAP_COORDS = 1,
   LBM_MAP_NEIGHBOURS = 2,
   LBM_MAP_FLUIDMASK = 3,
-  LBM_MAP_CANONICAL = 4
+  LBM_MAP_CANONICAL = 4,
+  LBM_MAP_BOUNDARY_BITS = 5,
+  LBM_MAP_RECORD_IDS = 6
 } lbm_map;
 lbm_status lbm_get_index_map(const lbm_grid *g, int32_t level, lbm_map which, void *host_out,
                              size_t *count);

@@ -305,10 +305,13 @@ def _face_voxel_kinds(nx, ny, nz, periodic, face_kinds, heavy):
     return m
 
 
-def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool):
+def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, grouped: bool = True):
     """Returns a dict with coords [nb,3], nbr [nb,18], fmask [nb] (uint64),
-    groups (n_boundary, n_masked, n_full), canon [nb*64] (int64, -1 = not
-    fluid), n_fluid."""
+    groups (n_boundary, n_masked, n_full), group [nb] (0 boundary, 1 masked,
+    2 full, per storage slot), canon [nb*64] (int64, -1 = not fluid),
+    n_fluid.  grouped: memory-based grouping (boundary, masked, full groups
+    stored one after the other, Morton order inside each); otherwise the
+    bitmask-based form keeps every block in one Morton order."""
     c, _, _ = lattice()
     B = 4
     assert nx % B == 0 and ny % B == 0 and nz % B == 0
@@ -357,8 +360,12 @@ def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool):
     for key in active:
         groups[group_of(*key)].append(key)
     order = []
-    for gid in (0, 1, 2):
-        order += sorted(groups[gid], key=lambda k: morton_key(*k))
+    if grouped:
+        for gid in (0, 1, 2):
+            order += sorted(groups[gid], key=lambda k: morton_key(*k))
+    else:
+        order = sorted(active, key=lambda k: morton_key(*k))
+    gid_of = {k: gid for gid in (0, 1, 2) for k in groups[gid]}
     slot_of = {k: s for s, k in enumerate(order)}
     nb = len(order)
     coords = np.array(order, np.int32).reshape(nb, 3)
@@ -389,6 +396,7 @@ def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool):
                     canon[s * 64 + lx + 4 * ly + 16 * lz] = v[lz, ly, lx]
     return dict(coords=coords, nbr=nbr, fmask=fmask,
                 groups=tuple(len(groups[g]) for g in (0, 1, 2)),
+                group=np.array([gid_of[k] for k in order], np.int32),
                 canon=canon, n_fluid=int(fl.sum()))
 
 

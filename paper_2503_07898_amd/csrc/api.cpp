@@ -53,6 +53,7 @@ struct LevelRT {
   int nbuf = 2;
   size_t off_pop[3] = {0, 0, 0};
   size_t off_nbr = 0, off_bbm = 0, off_coords = 0, off_canon = 0, off_jtab = 0, off_jlist = 0, off_fmask = 0;
+  size_t off_bbits = 0, off_vid = 0, off_vrec = 0;  // bitmask layout
   int64_t partial_row0 = 0;        // first row of this level in the reduction partials
   int cur = 0, prev = 2, nxt = 1;  // roles of the population buffers
   std::vector<int32_t> packed;
@@ -107,6 +108,11 @@ StepArgs level_args(const lbm_grid *g, const LevelRT &r) {
     a.bbm = (const uint64_t *)(g->ws + r.off_bbm);
     a.coords = (const int32_t *)(g->ws + r.off_coords);
     a.fmask = (const uint64_t *)(g->ws + r.off_fmask);
+    if (!r.L->grouped) {
+      a.bbits = (const uint32_t *)(g->ws + r.off_bbits);
+      a.vid = (const int32_t *)(g->ws + r.off_vid);
+      a.vrec = (const float *)(g->ws + r.off_vrec);
+    }
   }
   if (g->mlp) {
     a.mlp_w = g->mlp->B.wpacked;
@@ -167,6 +173,10 @@ void level_update(const lbm_grid *g, const std::vector<LevelRT> &lv, int l, int 
   if (!multires) {
     if (plain) {
       push(kKernelBoundary, 1, 0, nb);  // the naive single kernel
+    } else if (!r.L->grouped) {
+      // bitmask-based grouping: both kernels over every block
+      push(kKernelInteriorBits, 1, 0, nb);
+      push(kKernelBoundaryBits, 1, 0, nb);
     } else {
       // largest group first; the groups are independent within a step
       push(kKernelFull, 1, first[3], (int32_t)gc[3]);
@@ -256,8 +266,10 @@ lbm_status lbm_grid_create(const lbm_grid_desc *d, lbm_grid **out) {
   if (d->collision < LBM_BGK || d->collision > LBM_MLP) return fail(LBM_ERR_INVALID_ARG, "unknown collision");
   if (d->collision == LBM_MLP)
     return fail(LBM_ERR_UNSUPPORTED, "the MLP closure is selected with lbm_set_collision");
-  if (d->schedule != LBM_PLAIN_SINGLE_KERNEL && d->schedule != LBM_DISAGG)
+  if (d->schedule != LBM_PLAIN_SINGLE_KERNEL && d->schedule != LBM_DISAGG && d->schedule != LBM_DISAGG_BITMASK)
     return fail(LBM_ERR_INVALID_ARG, "unknown schedule");
+  if (d->schedule == LBM_DISAGG_BITMASK && d->kind == LBM_MULTIRES)
+    return fail(LBM_ERR_UNSUPPORTED, "bitmask-based grouping is built for dense and block-sparse grids");
   if (d->kind != LBM_DENSE && d->kind != LBM_BLOCK_SPARSE && d->kind != LBM_MULTIRES)
     return fail(LBM_ERR_INVALID_ARG, "unknown grid kind");
   if (d->kind != LBM_MULTIRES && d->num_levels != 1)
@@ -345,7 +357,7 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
     g->lv.push_back(r);
   } else if (d.kind != LBM_MULTIRES) {
     std::string e = build_block_level(g->single, d.nx, d.ny, d.nz, d.periodic, g->fluid, g->faces,
-                                      d.kind == LBM_DENSE);
+                                      d.kind == LBM_DENSE, nullptr, d.schedule != LBM_DISAGG_BITMASK);
     if (!e.empty()) return fail(LBM_ERR_INVALID_ARG, "%s", e.c_str());
     LevelRT r;
     r.L = &g->single;
@@ -394,6 +406,14 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
       off = align256(off + r.L->canon.size() * 4);
       r.off_fmask = off;
       off = align256(off + r.L->fmask.size() * 8);
+      if (!r.L->grouped) {
+        r.off_bbits = off;
+        off = align256(off + r.L->bbits.size() * 4);
+        r.off_vid = off;
+        off = align256(off + r.L->vid.size() * 4);
+        r.off_vrec = off;
+        off = align256(off + r.L->vrec.size() * 4);
+      }
     }
     if (r.M) {
       r.off_jtab = off;
@@ -430,6 +450,11 @@ lbm_status lbm_grid_bind(lbm_grid *g, void *ws, size_t bytes, void *stream) {
     up(r.off_coords, r.packed.data(), r.packed.size() * 4);
     up(r.off_canon, r.L->canon.data(), r.L->canon.size() * 4);
     up(r.off_fmask, r.L->fmask.data(), r.L->fmask.size() * 8);
+    if (!r.L->grouped) {
+      up(r.off_bbits, r.L->bbits.data(), r.L->bbits.size() * 4);
+      up(r.off_vid, r.L->vid.data(), r.L->vid.size() * 4);
+      up(r.off_vrec, r.L->vrec.data(), r.L->vrec.size() * 4);
+    }
     if (r.M) {
       up(r.off_jtab, r.M->jtab.data(), r.M->jtab.size() * 4);
       up(r.off_jlist, r.M->jlist.data(), r.M->jlist.size() * 4);
@@ -589,6 +614,8 @@ lbm_status lbm_get_index_map(const lbm_grid *g, int32_t level, lbm_map which, vo
       }
       break;
     }
+    case LBM_MAP_BOUNDARY_BITS: n = L.bbits.size(); if (out) memcpy(out, L.bbits.data(), n * 4); break;
+    case LBM_MAP_RECORD_IDS: n = L.vid.size(); if (out) memcpy(out, L.vid.data(), n * 4); break;
     default: return fail(LBM_ERR_INVALID_ARG, "unknown map");
   }
   *count = n;
@@ -789,6 +816,7 @@ lbm_status lbm_sample_populations(lbm_grid *g, int32_t level, uint64_t seed, int
   if (lbm_status st = check_level(g, level)) return st;
   const LevelRT &r = g->lv[level];
   if (!r.L) return fail(LBM_ERR_UNSUPPORTED, "sampling needs a block layout");
+  if (!r.L->grouped) return fail(LBM_ERR_UNSUPPORTED, "sampling needs the memory-grouped layout");
   const auto &gc = r.L->group_count;
   const int32_t b0 = (int32_t)(gc[0] + gc[1]), nb = (int32_t)(gc[2] + gc[3]);
   if (nb <= 0) return fail(LBM_ERR_INVALID_ARG, "the level has no non-boundary blocks");

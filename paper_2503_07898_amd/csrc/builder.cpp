@@ -1,7 +1,8 @@
 // Host grid builder: classification and locality mapping of the
 // disaggregated block layout (Definition 1, steps 2 and 3; block-sparse
 // grids managed by a space-filling curve; memory-based grouping with the
-// boundary group stored first).
+// boundary group stored first, or bitmask-based grouping with one Morton
+// order and indirect boundary records).
 #include <algorithm>
 #include <cstring>
 
@@ -31,7 +32,9 @@ static bool heavy_face(const FaceBC &f) {
 
 std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
                               const uint8_t periodic[3], const std::vector<uint8_t> &fluid,
-                              const FaceBC faces[6], bool dense, const std::vector<uint8_t> *jump) {
+                              const FaceBC faces[6], bool dense, const std::vector<uint8_t> *jump,
+                              bool grouped) {
+  if (!grouped && jump) return "the bitmask layout has no resolution jumps";
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 4 || ny % 4 || nz % 4)
     return "block grids need positive sizes that are multiples of 4";
   if (nx / 4 >= 1024 || ny / 4 >= 1024 || nz / 4 >= 1024)
@@ -120,18 +123,34 @@ std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
       }
 
   L.slot_of_block.assign(nbtot, -1);
+  L.grouped = grouped;
   std::vector<int64_t> order;
+  std::vector<uint8_t> gid_of(nbtot, 0);
   for (int g = 0; g < kNumGroups; ++g) {
     std::sort(grp[g].begin(), grp[g].end());
     L.group_count[g] = (int64_t)grp[g].size();
-    for (auto &kv : grp[g]) {
-      L.slot_of_block[kv.second] = (int32_t)order.size();
-      order.push_back(kv.second);
-    }
+    for (auto &kv : grp[g]) gid_of[kv.second] = (uint8_t)g;
   }
+  if (grouped) {
+    for (int g = 0; g < kNumGroups; ++g)
+      for (auto &kv : grp[g]) order.push_back(kv.second);
+  } else {
+    std::vector<std::pair<uint64_t, int64_t>> all;
+    for (int g = 0; g < kNumGroups; ++g) all.insert(all.end(), grp[g].begin(), grp[g].end());
+    std::sort(all.begin(), all.end());
+    for (auto &kv : all) order.push_back(kv.second);
+  }
+  for (size_t s = 0; s < order.size(); ++s) L.slot_of_block[order[s]] = (int32_t)s;
   L.nblocks = (int64_t)order.size();
   if (L.nblocks == 0) return "the grid has no fluid voxel";
   if (L.nblocks * 64 >= (int64_t)1 << 31) return "too many blocks for 32-bit slot indices";
+
+  L.group.resize(L.nblocks);
+  L.bbits.assign((L.nblocks + 31) / 32, 0u);
+  for (int64_t s = 0; s < L.nblocks; ++s) {
+    L.group[s] = gid_of[order[s]];
+    if (L.group[s] == kGroupBoundary) L.bbits[s >> 5] |= 1u << (s & 31);
+  }
 
   L.coords.resize(L.nblocks * 3);
   L.nbr.assign(L.nblocks * 18, -1);
@@ -177,6 +196,35 @@ std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
           L.canon[s * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)] = (int32_t)c++;
         }
   L.n_fluid = c;
+
+  if (!grouped) {
+    // indirect boundary records: every fluid voxel of a boundary block that
+    // lies on a moving-wall or regularized face gets one record holding that
+    // face's value (wall / inlet velocity, or outlet density in component 0)
+    L.vid.assign(L.nblocks * 64, -1);
+    for (int64_t s = 0; s < L.nblocks; ++s) {
+      if (L.group[s] != kGroupBoundary) continue;
+      const int bx = L.coords[3 * s], by = L.coords[3 * s + 1], bz = L.coords[3 * s + 2];
+      for (int l = 0; l < 64; ++l) {
+        if (!((L.fmask[s] >> l) & 1)) continue;
+        const int g[3] = {bx * 4 + (l & 3), by * 4 + ((l >> 2) & 3), bz * 4 + (l >> 4)};
+        const int n3[3] = {nx, ny, nz};
+        int valued = -1;
+        for (int f = 0; f < 6; ++f) {
+          const int a = f / 2;
+          if (periodic[a] || !heavy_face(faces[f])) continue;
+          if (g[a] != ((f & 1) ? n3[a] - 1 : 0)) continue;
+          if (valued >= 0) return "the bitmask layout needs every voxel on at most one moving-wall or regularized face";
+          valued = f;
+        }
+        if (valued < 0) continue;
+        L.vid[s * 64 + l] = (int32_t)(L.vrec.size() / 4);
+        for (int k = 0; k < 3; ++k) L.vrec.push_back((float)faces[valued].value[k]);
+        L.vrec.push_back(0.0f);
+      }
+    }
+    if (L.vrec.empty()) L.vrec.assign(4, 0.0f);  // keep the buffer non-empty
+  }
   return "";
 }
 

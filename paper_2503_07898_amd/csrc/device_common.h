@@ -226,9 +226,11 @@ __device__ __forceinline__ float moving_wall_term(const FaceParams &fp, int face
   return (6.0f * weight_f(I)) * cu;  // 2 w_i (c_i . u_w) / c_s^2, wall density 1
 }
 
-template <int I>
+// REC: the moving-wall velocity comes from the voxel's boundary record rv
+// (indirect indexing of the bitmask layout) instead of the face table.
+template <int I, bool REC = false>
 __device__ __forceinline__ LinkClass classify_link(const FaceParams &fp, int gx, int gy, int gz,
-                                                   int nx, int ny, int nz) {
+                                                   int nx, int ny, int nz, const float *rv = nullptr) {
   constexpr int c[3] = {kCx[I], kCy[I], kCz[I]};
   const int g[3] = {gx, gy, gz};
   const int n[3] = {nx, ny, nz};
@@ -244,7 +246,10 @@ __device__ __forceinline__ LinkClass classify_link(const FaceParams &fp, int gx,
     if (!crossed) continue;
     const int k = fp.kind[face];
     if (k == LBM_BC_MOVING_WALL) {
-      if (!moving) extra = moving_wall_term<I>(fp, face);
+      if (!moving) {
+        if constexpr (REC) extra = (6.0f * weight_f(I)) * cdotu<I>(rv[0], rv[1], rv[2]);
+        else extra = moving_wall_term<I>(fp, face);
+      }
       moving = true;
     } else if (k == LBM_BC_BOUNCE_BACK) {
       wall = true;
@@ -279,8 +284,11 @@ __device__ __forceinline__ int face_kind(const FaceParams &fp, int face) {
 // (pressure face) from the tangential and outgoing sums, rebuilds the unknown
 // populations by non-equilibrium bounce-back, regularizes and relaxes:
 // h* = h^eq + (1 - omega) f1.
+// REC: the face value comes from the voxel's boundary record rv.
+template <bool REC = false>
 __device__ __forceinline__ void regularized_face(float (&h)[Q], uint32_t unknown, int face,
-                                                 const FaceParams &fp, float omega) {
+                                                 const FaceParams &fp, float omega,
+                                                 const float *rv = nullptr) {
   const int axis = face >> 1;
   const float sgn = (face & 1) ? 1.0f : -1.0f;
   // per axis: sums over c_a = 0, c_a > 0 and c_a < 0 (index sets fixed at
@@ -302,15 +310,16 @@ __device__ __forceinline__ void regularized_face(float (&h)[Q], uint32_t unknown
   const float sO = (face & 1) ? sOp : sOm;  // populations leaving through the face
   const float X = sT + 2.0f * sO;  // = rho (1 + u.n) - 1
   Moments m;
+  auto value = [&](int k) { return REC ? rv[k] : face_val(fp, face, k); };
   if (face_kind(fp, face) == LBM_BC_REG_VELOCITY) {
-    m.ux = face_val(fp, face, 0);
-    m.uy = face_val(fp, face, 1);
-    m.uz = face_val(fp, face, 2);
+    m.ux = value(0);
+    m.uy = value(1);
+    m.uz = value(2);
     const float un = sgn * (axis == 0 ? m.ux : (axis == 1 ? m.uy : m.uz));
     m.drho = (X - un) / (1.0f + un);
     m.rho = 1.0f + m.drho;
   } else {
-    m.rho = face_val(fp, face, 0);
+    m.rho = value(0);
     m.drho = m.rho - 1.0f;
     const float un = (X - m.drho) / m.rho;
     m.ux = axis == 0 ? sgn * un : 0.0f;

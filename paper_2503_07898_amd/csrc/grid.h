@@ -40,6 +40,12 @@ struct BlockLevel {
   std::vector<int32_t> canon;      // [nblocks*64]: canonical index or -1
   std::vector<int32_t> slot_of_block;  // [nbz][nby][nbx] -> block slot or -1
   int64_t n_fluid = 0;
+  bool grouped = true;             // memory-based grouping (else one Morton order)
+  std::vector<uint8_t> group;      // [nblocks] BlockGroup of each storage slot
+  std::vector<uint32_t> bbits;     // [(nblocks+31)/32] bit set = boundary-group block
+  // bitmask layout only: indirect boundary records
+  std::vector<int32_t> vid;        // [nblocks*64] record of the voxel, -1 = none
+  std::vector<float> vrec;         // [nrec][4] value of the voxel's valued face (u or rho), 0
 };
 
 uint64_t morton_key(uint32_t bx, uint32_t by, uint32_t bz);
@@ -51,10 +57,12 @@ uint64_t morton_key(uint32_t bx, uint32_t by, uint32_t bz);
 // regularized face form the boundary group.  Returns "" or an error message.
 // `jump` (optional, same shape as fluid) marks voxels next to a resolution
 // jump; blocks holding one form the first group.
+// `grouped` = false keeps all blocks in one Morton order (bitmask-based
+// grouping) and builds the per-voxel indirect ids and boundary records.
 std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
                               const uint8_t periodic[3], const std::vector<uint8_t> &fluid,
                               const FaceBC faces[6], bool dense,
-                              const std::vector<uint8_t> *jump = nullptr);
+                              const std::vector<uint8_t> *jump = nullptr, bool grouped = true);
 
 // ---------------------------------------------------------------- multires
 // Source-list entry of the jump tables: bits 31..29 buffer tag, bit 28 use

@@ -32,6 +32,10 @@ struct StepArgs {
   const float *mlp_bias;          // b1 | b2 | b3
   const float *mlp_stdz;          // in_mean | in_inv_std | out_std | out_mean (32 each)
   unsigned int *mlp_fallbacks;    // voxels that fell back to the regularized operator
+  // bitmask-based grouping
+  const uint32_t *bbits;          // [(nblocks+31)/32] bit set = boundary block
+  const int32_t *vid;             // [S] boundary record of the slot, -1 = none
+  const float *vrec;              // [nrec][4] record values
 };
 
 enum KernelKind : int32_t {
@@ -41,7 +45,9 @@ enum KernelKind : int32_t {
   kKernelJump = 3,          // multires blocks next to a resolution jump (table gather)
   kKernelCollide = 4,       // collision only, in place (unfused multires baseline)
   kKernelCollideHeavy = 5,  // collision only for heavy-boundary blocks
-  kKernelLex = 6            // dense lexicographic single kernel
+  kKernelLex = 6,           // dense lexicographic single kernel
+  kKernelInteriorBits = 7,  // bitmask grouping: all blocks, non-boundary ones processed
+  kKernelBoundaryBits = 8   // bitmask grouping: all blocks, boundary ones processed
 };
 
 // Sources of the multires jump gather, indexed by table tag: own level now,

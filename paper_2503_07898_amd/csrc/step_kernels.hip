@@ -57,12 +57,10 @@ __device__ __forceinline__ void collide(float (&h)[Q], float omega) {
 }
 
 // ------------------------------------------------------ interior kernels --
+// Per-block body of the interior kernels (b is wave-uniform).
 template <class ST, int COLL, bool MASKED, bool FUSED>
-__global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, int32_t n) {
+__device__ __forceinline__ void interior_block(const StepArgs &a, int b) {
   using T = typename ST::T;
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
-  if (b >= g0 + n) return;
   const int lane = threadIdx.x & 63;
   const T *__restrict__ src = (const T *)a.src;
   T *__restrict__ dst = (T *)a.dst;
@@ -97,6 +95,26 @@ __global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, 
 
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+}
+
+template <class ST, int COLL, bool MASKED, bool FUSED>
+__global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, int32_t n) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  interior_block<ST, COLL, MASKED, FUSED>(a, b);
+}
+
+// Bitmask-based grouping: every block of the level is visited, the run-time
+// bit of the block selects the non-boundary ones (bounce masks cover the
+// blocks that the memory-based layout separates as "full").
+template <class ST, int COLL>
+__global__ __launch_bounds__(256) void k_block_interior_bits(StepArgs a, int32_t g0, int32_t n) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  if ((a.bbits[b >> 5] >> (b & 31)) & 1u) return;
+  interior_block<ST, COLL, true, true>(a, b);
 }
 
 // ------------------------------------------ interior kernel, learned closure --
@@ -183,12 +201,11 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
 }
 
 // ------------------------------------------------------ boundary kernel --
-template <class ST, int COLL, bool FUSED>
-__global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, int32_t n) {
+// Per-block body of the boundary kernels.  REC: boundary values from the
+// voxel's indirect record (bitmask layout) instead of the face table.
+template <class ST, int COLL, bool FUSED, bool REC>
+__device__ __forceinline__ void boundary_block(const StepArgs &a, int b) {
   using T = typename ST::T;
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
-  if (b >= g0 + n) return;
   const int lane = threadIdx.x & 63;
   const T *__restrict__ src = (const T *)a.src;
   T *__restrict__ dst = (T *)a.dst;
@@ -207,13 +224,23 @@ __global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, 
   const int gy = ((packed >> 10) & 1023) * 4 + ((lane >> 2) & 3);
   const int gz = ((packed >> 20) & 1023) * 4 + (lane >> 4);
 
+  float rv[3] = {0.0f, 0.0f, 0.0f};
+  if constexpr (REC) {
+    const int32_t id = a.vid[own_slot];
+    if (id >= 0) {
+      rv[0] = a.vrec[4 * id];
+      rv[1] = a.vrec[4 * id + 1];
+      rv[2] = a.vrec[4 * id + 2];
+    }
+  }
+
   float h[Q];
   uint32_t unknown = 0;
   int rface = 0;
   h[0] = ST::load(src, own_slot);
   static_for<1, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    const LinkClass lc = classify_link<i>(a.fp, gx, gy, gz, a.nx, a.ny, a.nz);
+    const LinkClass lc = classify_link<i, REC>(a.fp, gx, gy, gz, a.nx, a.ny, a.nz, rv);
     uint32_t slot = pull_slot<i>(lane, b, nbv);
     uint32_t plane = i;
     if (lc.kind != kLinkInside || ((bm[i - 1] >> lane) & 1ull)) {
@@ -230,12 +257,30 @@ __global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, 
   });
 
   if constexpr (FUSED) {
-    if (unknown) regularized_face(h, unknown, rface, a.fp, a.omega);
+    if (unknown) regularized_face<REC>(h, unknown, rface, a.fp, a.omega, rv);
     else collide<COLL>(h, a.omega);
   }
 
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+}
+
+template <class ST, int COLL, bool FUSED>
+__global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, int32_t n) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  boundary_block<ST, COLL, FUSED, false>(a, b);
+}
+
+// Bitmask-based grouping: visits every block, keeps the boundary ones.
+template <class ST, int COLL>
+__global__ __launch_bounds__(256) void k_block_boundary_bits(StepArgs a, int32_t g0, int32_t n) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  if (!((a.bbits[b >> 5] >> (b & 31)) & 1u)) return;
+  boundary_block<ST, COLL, true, true>(a, b);
 }
 
 // ------------------------------------------------- collision-only kernel --
@@ -468,6 +513,12 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
       break;
     case kKernelCollide:
       hipLaunchKernelGGL((k_block_collide<ST, COLL, false>), grd, blk, 0, s, L.args, g0, n);
+      break;
+    case kKernelInteriorBits:
+      hipLaunchKernelGGL((k_block_interior_bits<ST, COLL>), grd, blk, 0, s, L.args, g0, n);
+      break;
+    case kKernelBoundaryBits:
+      hipLaunchKernelGGL((k_block_boundary_bits<ST, COLL>), grd, blk, 0, s, L.args, g0, n);
       break;
     case kKernelCollideHeavy:
       hipLaunchKernelGGL((k_block_collide<ST, COLL, true>), grd, blk, 0, s, L.args, g0, n);

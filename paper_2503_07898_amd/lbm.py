@@ -21,10 +21,10 @@ LBM_OK = 0
 DENSE, BLOCK_SPARSE, MULTIRES = 0, 1, 2
 F32, F16_SHIFTED, BF16_SHIFTED = 0, 1, 2
 BGK, REGULARIZED, MLP = 0, 1, 2
-PLAIN_SINGLE_KERNEL, DISAGG = 0, 1
+PLAIN_SINGLE_KERNEL, DISAGG, DISAGG_BITMASK = 0, 1, 2
 XMIN, XMAX, YMIN, YMAX, ZMIN, ZMAX = range(6)
 BC_BOUNCE_BACK, BC_MOVING_WALL, BC_REG_VELOCITY, BC_REG_PRESSURE = range(4)
-MAP_GROUPS, MAP_COORDS, MAP_NEIGHBOURS, MAP_FLUIDMASK, MAP_CANONICAL = range(5)
+MAP_GROUPS, MAP_COORDS, MAP_NEIGHBOURS, MAP_FLUIDMASK, MAP_CANONICAL, MAP_BOUNDARY_BITS, MAP_RECORD_IDS = range(7)
 
 STORAGE_BYTES = {F32: 4, F16_SHIFTED: 2, BF16_SHIFTED: 2}
 
@@ -172,7 +172,8 @@ def lbm_get_index_map(g, level: int, which: int) -> np.ndarray:
     n = ctypes.c_size_t()
     check(lib().lbm_get_index_map(g, level, which, None, ctypes.byref(n)))
     dtype = {MAP_GROUPS: np.int64, MAP_COORDS: np.int32, MAP_NEIGHBOURS: np.int32,
-             MAP_FLUIDMASK: np.uint64, MAP_CANONICAL: np.int64}[which]
+             MAP_FLUIDMASK: np.uint64, MAP_CANONICAL: np.int64, MAP_BOUNDARY_BITS: np.uint32,
+             MAP_RECORD_IDS: np.int32}[which]
     out = np.zeros(n.value, dtype)
     check(lib().lbm_get_index_map(g, level, which, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
     return out

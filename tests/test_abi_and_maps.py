@@ -168,3 +168,71 @@ def test_launch_structure_table_dissBlock():
     assert gb == 2 * (n[1] // 4) * (n[2] // 4)  # inlet and outlet block layers
     # memory grouping needs no boundary metadata: the two arms have the same workspace
     assert naive.workspace_bytes == disagg.workspace_bytes
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("seed", [0, 1])
+def test_bitmask_layout_maps(orc, case, seed):
+    """Bitmask-based grouping: one Morton order over all blocks, the boundary
+    bit of every block equal to the reference builder's classification, and
+    one indirect record per fluid voxel of a boundary block on a moving-wall
+    or regularized face, numbered in slot order."""
+    n, periodic, kinds, dense = CASES[case]
+    fluid = None if dense else workloads.random_mask(*n, seed=seed + 10 * case, solid_fraction=0.15,
+                                                     empty_block_fraction=0.25)
+    g = lbm.Grid(*n, kind=lbm.DENSE if dense else lbm.BLOCK_SPARSE, periodic=periodic, fluid=fluid,
+                 faces=_faces(periodic, kinds), schedule=lbm.DISAGG_BITMASK, device="cpu")
+    okinds = [{"bb": orc.BB, "moving": orc.MOVING, "vel": orc.REG_VEL, "pres": orc.REG_PRES}[k]
+              for k in kinds]
+    ref = orc.build_block_maps(*n, periodic, fluid, okinds, dense, grouped=False)
+    nb = int(g.index_map(lbm.MAP_GROUPS)[4])
+    coords = g.index_map(lbm.MAP_COORDS).reshape(nb, 3)
+    assert np.array_equal(coords, ref["coords"])
+    keys = [orc.morton_key(*c) for c in coords]
+    assert keys == sorted(keys)
+    assert np.array_equal(g.index_map(lbm.MAP_NEIGHBOURS).reshape(nb, 18), ref["nbr"])
+    assert np.array_equal(g.index_map(lbm.MAP_CANONICAL), ref["canon"])
+    bits = g.index_map(lbm.MAP_BOUNDARY_BITS)
+    is_b = np.array([(int(bits[b >> 5]) >> (b & 31)) & 1 for b in range(nb)], bool)
+    assert np.array_equal(is_b, ref["group"] == 0)
+    ids = g.index_map(lbm.MAP_RECORD_IDS)
+    fmask = g.index_map(lbm.MAP_FLUIDMASK)
+    want, nrec = np.full(nb * 64, -1, np.int32), 0
+    valued = [f for f in range(6) if not periodic[f // 2] and kinds[f] != "bb"]
+    for b in range(nb):
+        if not is_b[b]:
+            continue
+        for l in range(64):
+            if not (int(fmask[b]) >> l) & 1:
+                continue
+            p = (coords[b, 0] * 4 + (l & 3), coords[b, 1] * 4 + ((l >> 2) & 3), coords[b, 2] * 4 + (l >> 4))
+            if any(p[f // 2] == (n[f // 2] - 1 if f & 1 else 0) for f in valued):
+                want[b * 64 + l] = nrec
+                nrec += 1
+    assert np.array_equal(ids, want)
+    g.close()
+    # the memory-grouped layout carries no records
+    m = lbm.Grid(*n, kind=lbm.DENSE if dense else lbm.BLOCK_SPARSE, periodic=periodic, fluid=fluid,
+                 faces=_faces(periodic, kinds), device="cpu")
+    assert m.index_map(lbm.MAP_RECORD_IDS).size == 0
+    m.close()
+
+
+def test_launch_structure_bitmask_grouping():
+    """Table dissBlock, bitmask row: two kernels, each over n_b + n_nb blocks,
+    and s_i (4 bytes) of indirect index per slot of every block."""
+    n = (32, 16, 16)
+    fluid, _ = workloads.sphere_packing(*n, seed=5, rmin=2, rmax=5, target_active=0.7)
+    faces = {lbm.XMIN: (lbm.BC_REG_VELOCITY, (0.05, 0, 0)), lbm.XMAX: (lbm.BC_REG_PRESSURE, (1, 0, 0))}
+    for f in (lbm.YMIN, lbm.YMAX, lbm.ZMIN, lbm.ZMAX):
+        faces[f] = (lbm.BC_BOUNCE_BACK, (0, 0, 0))
+    common = dict(kind=lbm.BLOCK_SPARSE, periodic=(False, False, False), fluid=fluid, faces=faces,
+                  device="cpu")
+    bits = lbm.Grid(*n, schedule=lbm.DISAGG_BITMASK, **common)
+    mem = lbm.Grid(*n, schedule=lbm.DISAGG, **common)
+    total = int(bits.index_map(lbm.MAP_GROUPS)[4])
+    assert bits.launches() == [total, total]
+    assert bits.workspace_bytes >= mem.workspace_bytes + 4 * 64 * total
+    with pytest.raises(lbm.LbmError):
+        lbm.Grid(*n, schedule=lbm.DISAGG_BITMASK, kind=lbm.MULTIRES, levels=2,
+                 level_map=np.zeros(n[::-1], np.uint8), device="cpu")

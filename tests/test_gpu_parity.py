@@ -126,7 +126,7 @@ def test_cavity_plain_vs_disagg_vs_oracle(orc, storage, bar):
     faces = cavity_faces()
     ro, uo = run_oracle(orc, n, steps, rho, u, periodic=(False,) * 3, faces=faces, tau=tau)
     pops = []
-    for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG):
+    for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG, lbm.DISAGG_BITMASK):
         g, r, v = run_gpu(n, steps, rho, u, kind=lbm.DENSE, periodic=(False,) * 3, faces=faces,
                           tau=tau, storage=storage, schedule=sch)
         err = rel(v, uo)
@@ -138,6 +138,7 @@ def test_cavity_plain_vs_disagg_vs_oracle(orc, storage, bar):
             assert gb == 8 ** 3 - 6 ** 3 and gf == 6 ** 3 and gm == 0
         g.close()
     assert np.array_equal(pops[0], pops[1])
+    assert np.array_equal(pops[0], pops[2])
 
 
 def test_cavity_mass_conserved_fp64_reduction():
@@ -181,7 +182,7 @@ def test_sparse_tunnel_vs_oracle(orc, storage, bar, collision):
     ro, uo = run_oracle(orc, n, steps, rho, u, fluid=fluid, periodic=(False,) * 3, faces=faces,
                         tau=tau, collision=collision)
     pops = []
-    for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG):
+    for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG, lbm.DISAGG_BITMASK):
         g, r, v = run_gpu(n, steps, rho, u, fluid=fluid, kind=lbm.BLOCK_SPARSE, periodic=(False,) * 3,
                           faces=faces, tau=tau, storage=storage, schedule=sch, collision=collision)
         err = rel(v, uo)
@@ -189,8 +190,10 @@ def test_sparse_tunnel_vs_oracle(orc, storage, bar, collision):
         assert err < bar
         pops.append(g.populations().cpu().numpy())
         g.close()
-    # the single heavy kernel and the grouped kernels run the same arithmetic
+    # the single heavy kernel and the grouped kernels (memory- or bitmask-
+    # based, face table or indirect records) run the same arithmetic
     assert np.array_equal(pops[0], pops[1])
+    assert np.array_equal(pops[0], pops[2])
 
 
 def test_sparse_all_active_equals_dense_bitwise():
