@@ -9,11 +9,16 @@ standardized non-equilibrium part of a voxel per unit density,
 g = (f - f^eq(rho, u)) / rho, to an estimate y of the regularized
 non-equilibrium part per unit density, f1/rho (the Hermite projection of
 the regularized collision).  The
-estimate is projected so that it carries no mass and no momentum,
+estimate is projected onto the second-order Hermite space, the space the
+regularized operator's f1 lives in,
 
-    P(y)_i = y_i - w_i sum_j y_j - w_i c_i . (sum_j c_j y_j) / c_s^2,
+    P(y)_i = w_i / (2 c_s^4) Q_i : sum_j Q_j y_j,   Q_i = c_i c_i - c_s^2 I,
 
-and the post-collision state is f* = f^eq + (1 - 1/tau) rho P(y).  A voxel
+so that it carries no mass, no momentum and no non-hydrodynamic (ghost)
+content, and the post-collision state is f* = f^eq + (1 - 1/tau) rho P(y).
+(The network thus supplies the non-equilibrium stress; a projection that
+only removed mass and momentum let ghost content through, which near
+tau = 1/2 is relaxed with a factor close to -1 and grew in closed loop.)  A voxel
 falls back to the regularized operator if any standardized input exceeds 8
 in magnitude or any output population is negative.  Training minimizes the
 mean squared error between P(y) and f1/rho, divided by the mean target
@@ -50,18 +55,25 @@ def lattice():
     return c.astype(np.float64), w
 
 
+def hermite_tensors():
+    """Q_i = c_i c_i - c_s^2 I for every direction, shape (19, 3, 3)."""
+    c, _ = lattice()
+    return np.einsum("ia,ib->iab", c, c) - np.eye(3)[None] / 3.0
+
+
 def projection_matrix():
-    """M with P(y) = y M^T for row vectors y (P_i = sum_j M_ij y_j)."""
-    c, w = lattice()
-    return np.eye(Q) - np.outer(w, np.ones(Q)) - 3.0 * np.outer(w, np.ones(Q)) * (c @ c.T)
+    """M with P(y) = y M^T for row vectors y: M_ij = w_i (Q_i : Q_j) / (2 c_s^4)."""
+    _, w = lattice()
+    Qt = hermite_tensors()
+    return 4.5 * w[:, None] * np.einsum("iab,jab->ij", Qt, Qt)
 
 
 def project(y):
-    c, w = lattice()
-    y = np.asarray(y, np.float64)
-    s = y.sum(-1, keepdims=True)
-    j = y @ c  # (..., 3)
-    return y - w * s - 3.0 * w * (j @ c.T)
+    """Second-order Hermite projection of y (..., 19)."""
+    _, w = lattice()
+    Qt = hermite_tensors()
+    pi = np.einsum("...j,jab->...ab", np.asarray(y, np.float64), Qt)
+    return 4.5 * w * np.einsum("iab,...ab->...i", Qt, pi)
 
 
 @dataclass

@@ -65,13 +65,21 @@ def test_projection_moments_and_idempotence(orc, mlp):
     py = mlp.project(y)
     assert np.max(np.abs(py.sum(-1))) < 1e-14
     assert np.max(np.abs(py @ c)) < 1e-14
-    assert np.allclose(mlp.project(py), py, atol=1e-15, rtol=0)
+    assert np.allclose(mlp.project(py), py, atol=1e-14, rtol=0)
     # the regularized target already carries no mass or momentum
     f = sample_populations(orc, 20, 3)
     t = mlp.regularized_target(f)
     assert np.allclose(mlp.project(t), t, atol=1e-16, rtol=0)
     # P as a matrix equals P as a function
     assert np.allclose(y @ mlp.projection_matrix().T, py, atol=1e-14, rtol=0)
+    # P keeps exactly the 6-dimensional second-order Hermite space: projecting
+    # a non-equilibrium part gives the regularized operator's f1 (the C
+    # oracle's own projection), and the 13 other w-orthogonal modes vanish
+    assert np.linalg.matrix_rank(mlp.projection_matrix(), tol=1e-12) == 6
+    g = mlp.closure_inputs(f)
+    assert np.allclose(mlp.project(g), t, atol=1e-15, rtol=0)
+    cubic = w * (c[:, 0] * c[:, 1] ** 2)  # a third-order (ghost) moment direction
+    assert np.max(np.abs(mlp.project(cubic))) < 1e-16
 
 
 def test_gelu(mlp):
