@@ -1,5 +1,5 @@
 /*
- * FP64 CPU oracle for the D3Q19 collide-and-stream update.
+ * FP64 CPU oracle for the D3Q19 (and D3Q27) collide-and-stream update.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
  * statement of what the GPU library computes.  It shares no code, header,
@@ -37,6 +37,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Built twice: as the D3Q19 oracle (default) and, with -DORC_D3Q27, as the
+ * D3Q27 oracle (the lattice of the paper's block-sparse register study). */
+#ifndef ORC_D3Q27
 #define ORC_Q 19
 
 /* Reading: direction order 0 rest, 1-6 faces (+x,-x,+y,-y,+z,-z), 7-18 edges,
@@ -53,6 +56,28 @@ static const double orc_w[ORC_Q] = {
     1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+#else
+#define ORC_Q 27
+
+/* Reading: the D3Q19 order followed by the 8 corners in opposite pairs
+ * (19,20),...,(25,26); weights 8/27, 2/27, 1/54, 1/216 (textbook D3Q27). */
+static const int orc_c[ORC_Q][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+
+static const double orc_w[ORC_Q] = {
+    8.0 / 27.0,
+    2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,
+    1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+    1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+    1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0,
+    1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0};
+#endif
 
 static const double orc_cs2 = 1.0 / 3.0;
 

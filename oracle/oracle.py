@@ -5,7 +5,8 @@ leg of bench.py import this module.  It shares no code with the GPU library
 (paper_2503_07898_amd/) and never imports it.
 
 Contents
-  * ctypes binding of lbm_oracle.c (the D3Q19 solver, see that file's header);
+  * ctypes binding of lbm_oracle.c (the D3Q19 solver, see that file's header,
+    and the same file built for D3Q27);
   * the reference builder of the disaggregated index maps (block ids, Morton
     order per group, neighbour tables, canonical order), written as a direct
     coordinate search (sections "Disaggregation on a Sparse Domain" and
@@ -24,6 +25,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+LIB27_PATH = os.path.join(HERE, "liboracle27.so")
 SRC_PATH = os.path.join(HERE, "lbm_oracle.c")
 SRC_MR_PATH = os.path.join(HERE, "lbm_oracle_multires.c")
 Q = 19
@@ -35,16 +37,17 @@ BGK, REGULARIZED = 0, 1
 
 
 def build(force: bool = False) -> str:
-    """Compile lbm_oracle.c with gcc (-O3 -fopenmp) into liboracle.so."""
-    if force or not os.path.exists(LIB_PATH) or (
-        os.path.getmtime(LIB_PATH) < max(os.path.getmtime(SRC_PATH), os.path.getmtime(SRC_MR_PATH))
-    ):
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-             "-Wall", "-Wextra", "-o", tmp, SRC_PATH, SRC_MR_PATH, "-lm"]
-        )
-        os.replace(tmp, LIB_PATH)
+    """Compile lbm_oracle.c (+ the multires file) with gcc (-O3 -fopenmp) into
+    liboracle.so, and lbm_oracle.c with -DORC_D3Q27 into liboracle27.so."""
+    newest = max(os.path.getmtime(SRC_PATH), os.path.getmtime(SRC_MR_PATH))
+    for path, extra in ((LIB_PATH, [SRC_PATH, SRC_MR_PATH]), (LIB27_PATH, ["-DORC_D3Q27", SRC_PATH])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < newest:
+            tmp = path + ".tmp"
+            subprocess.check_call(
+                ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                 "-Wall", "-Wextra", "-o", tmp] + extra + ["-lm"]
+            )
+            os.replace(tmp, path)
     return LIB_PATH
 
 
@@ -74,14 +77,15 @@ class _MrGrid(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(q: int = 19):
+    """The oracle library for lattice q (19 or 27)."""
+    if q not in _libs:
+        assert q in (19, 27), q
         build()
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH if q == 19 else LIB27_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
         gp = ctypes.POINTER(_Grid)
         L.orc_step.argtypes = [gp, dp, dp]
@@ -103,13 +107,14 @@ def lib():
         L.orc_collide_regularized.restype = None
         L.orc_f1.argtypes = [dp, dp, dp]
         L.orc_f1.restype = None
-        pp = ctypes.POINTER(ctypes.POINTER(ctypes.c_double))
-        L.orc_mr_run.argtypes = [ctypes.POINTER(_MrGrid), pp, pp, pp, ctypes.c_int32,
-                                 ctypes.POINTER(ctypes.c_int32)]
-        L.orc_mr_mass.argtypes = [ctypes.POINTER(_MrGrid), pp]
-        L.orc_mr_mass.restype = ctypes.c_double
-        _lib = L
-    return _lib
+        if q == 19:
+            pp = ctypes.POINTER(ctypes.POINTER(ctypes.c_double))
+            L.orc_mr_run.argtypes = [ctypes.POINTER(_MrGrid), pp, pp, pp, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)]
+            L.orc_mr_mass.argtypes = [ctypes.POINTER(_MrGrid), pp]
+            L.orc_mr_mass.restype = ctypes.c_double
+        _libs[q] = L
+    return _libs[q]
 
 
 def _dp(a: np.ndarray):
@@ -117,20 +122,20 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def lattice():
-    """(c [19,3] int, w [19] float64, opp [19] int) as the oracle defines them."""
-    c = np.zeros((Q, 3), np.int32)
-    w = np.zeros(Q, np.float64)
-    opp = np.zeros(Q, np.int32)
-    lib().orc_lattice(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(w),
-                      opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+def lattice(q: int = 19):
+    """(c [q,3] int, w [q] float64, opp [q] int) as the oracle defines them."""
+    c = np.zeros((q, 3), np.int32)
+    w = np.zeros(q, np.float64)
+    opp = np.zeros(q, np.int32)
+    lib(q).orc_lattice(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(w),
+                       opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return c, w, opp
 
 
-def equilibrium(rho: float, u) -> np.ndarray:
+def equilibrium(rho: float, u, q: int = 19) -> np.ndarray:
     u = np.ascontiguousarray(u, np.float64)
-    out = np.zeros(Q)
-    lib().orc_equilibrium(float(rho), _dp(u), _dp(out))
+    out = np.zeros(q)
+    lib(q).orc_equilibrium(float(rho), _dp(u), _dp(out))
     return out
 
 
@@ -138,29 +143,29 @@ def moments(f) -> tuple[float, np.ndarray]:
     f = np.ascontiguousarray(f, np.float64)
     r = np.zeros(1)
     u = np.zeros(3)
-    lib().orc_moments(_dp(f), _dp(r), _dp(u))
+    lib(f.shape[-1]).orc_moments(_dp(f), _dp(r), _dp(u))
     return float(r[0]), u
 
 
 def collide_bgk(f, tau: float) -> np.ndarray:
     f = np.ascontiguousarray(f, np.float64)
-    out = np.zeros(Q)
-    lib().orc_collide_bgk(_dp(f), float(tau), _dp(out))
+    out = np.zeros(f.shape[-1])
+    lib(f.shape[-1]).orc_collide_bgk(_dp(f), float(tau), _dp(out))
     return out
 
 
 def collide_regularized(f, tau: float) -> np.ndarray:
     f = np.ascontiguousarray(f, np.float64)
-    out = np.zeros(Q)
-    lib().orc_collide_regularized(_dp(f), float(tau), _dp(out))
+    out = np.zeros(f.shape[-1])
+    lib(f.shape[-1]).orc_collide_regularized(_dp(f), float(tau), _dp(out))
     return out
 
 
 def f1_projection(f, feq) -> np.ndarray:
     f = np.ascontiguousarray(f, np.float64)
     feq = np.ascontiguousarray(feq, np.float64)
-    out = np.zeros(Q)
-    lib().orc_f1(_dp(f), _dp(feq), _dp(out))
+    out = np.zeros(f.shape[-1])
+    lib(f.shape[-1]).orc_f1(_dp(f), _dp(feq), _dp(out))
     return out
 
 
@@ -179,6 +184,7 @@ class Grid:
     bc: list = field(default_factory=lambda: [(BB, (0.0, 0.0, 0.0))] * 6)
     tau: float = 0.6
     collision: int = BGK
+    q: int = 19  # lattice: 19 or 27
 
     def _struct(self):
         g = _Grid()
@@ -211,18 +217,18 @@ class Grid:
         return np.asarray(self.fluid, bool)
 
     def init_equilibrium(self, rho, u) -> np.ndarray:
-        """rho (nz,ny,nx), u (nz,ny,nx,3) -> f (nz,ny,nx,19)."""
+        """rho (nz,ny,nx), u (nz,ny,nx,3) -> f (nz,ny,nx,q)."""
         rho = np.ascontiguousarray(np.broadcast_to(rho, (self.nz, self.ny, self.nx)), np.float64)
         u = np.ascontiguousarray(np.broadcast_to(u, (self.nz, self.ny, self.nx, 3)), np.float64)
-        f = np.zeros((self.nz, self.ny, self.nx, Q))
+        f = np.zeros((self.nz, self.ny, self.nx, self.q))
         g = self._struct()
-        lib().orc_init_equilibrium(ctypes.byref(g), _dp(rho), _dp(u), _dp(f))
+        lib(self.q).orc_init_equilibrium(ctypes.byref(g), _dp(rho), _dp(u), _dp(f))
         return f
 
     def step(self, f: np.ndarray) -> np.ndarray:
         out = np.zeros_like(f)
         g = self._struct()
-        r = lib().orc_step(ctypes.byref(g), _dp(f), _dp(out))
+        r = lib(self.q).orc_step(ctypes.byref(g), _dp(f), _dp(out))
         if r != 0:
             raise ValueError("oracle: a link crosses two regularized faces")
         return out
@@ -231,16 +237,16 @@ class Grid:
         f = np.array(f, np.float64, order="C", copy=True)
         work = np.zeros_like(f)
         g = self._struct()
-        r = lib().orc_run(ctypes.byref(g), _dp(f), _dp(work), int(nsteps))
+        r = lib(self.q).orc_run(ctypes.byref(g), _dp(f), _dp(work), int(nsteps))
         if r != 0:
             raise ValueError("oracle: a link crosses two regularized faces")
         return f
 
     def step_voxels(self, f: np.ndarray, vox: np.ndarray) -> np.ndarray:
         vox = np.ascontiguousarray(vox, np.int64)
-        out = np.zeros((len(vox), Q))
+        out = np.zeros((len(vox), self.q))
         g = self._struct()
-        r = lib().orc_step_voxels(ctypes.byref(g), _dp(f),
+        r = lib(self.q).orc_step_voxels(ctypes.byref(g), _dp(f),
                                   vox.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                   len(vox), _dp(out))
         if r != 0:
@@ -251,7 +257,7 @@ class Grid:
         rho = np.zeros((self.nz, self.ny, self.nx))
         u = np.zeros((self.nz, self.ny, self.nx, 3))
         g = self._struct()
-        lib().orc_macroscopic(ctypes.byref(g), _dp(f), _dp(rho), _dp(u))
+        lib(self.q).orc_macroscopic(ctypes.byref(g), _dp(f), _dp(rho), _dp(u))
         return rho, u
 
 
@@ -305,14 +311,16 @@ def _face_voxel_kinds(nx, ny, nz, periodic, face_kinds, heavy):
     return m
 
 
-def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, grouped: bool = True):
+def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, grouped: bool = True,
+                     q: int = 19):
     """Returns a dict with coords [nb,3], nbr [nb,18], fmask [nb] (uint64),
     groups (n_boundary, n_masked, n_full), group [nb] (0 boundary, 1 masked,
     2 full, per storage slot), canon [nb*64] (int64, -1 = not fluid),
     n_fluid.  grouped: memory-based grouping (boundary, masked, full groups
     stored one after the other, Morton order inside each); otherwise the
-    bitmask-based form keeps every block in one Morton order."""
-    c, _, _ = lattice()
+    bitmask-based form keeps every block in one Morton order.  q: lattice
+    (19: 18 face/edge neighbours; 27: 26 with the corners)."""
+    c, _, _ = lattice(q)
     B = 4
     assert nx % B == 0 and ny % B == 0 and nz % B == 0
     nbx, nby, nbz = nx // B, ny // B, nz // B
@@ -330,14 +338,14 @@ def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, group
                     active[(bx, by, bz)] = True
 
     def neighbour(bx, by, bz, d):
-        q = [bx + c[d, 0], by + c[d, 1], bz + c[d, 2]]
+        t = [bx + c[d, 0], by + c[d, 1], bz + c[d, 2]]
         nb = (nbx, nby, nbz)
         for a in range(3):
-            if q[a] < 0 or q[a] >= nb[a]:
+            if t[a] < 0 or t[a] >= nb[a]:
                 if not periodic[a]:
                     return None
-                q[a] %= nb[a]
-        return tuple(q) if tuple(q) in active else None
+                t[a] %= nb[a]
+        return tuple(t) if tuple(t) in active else None
 
     def group_of(bx, by, bz):
         if dense:
@@ -350,7 +358,7 @@ def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, group
             return 0
         # full: every source of every voxel in the block is a fluid voxel
         full = block_view(fl, bx, by, bz).all()
-        for d in range(1, 19):
+        for d in range(1, q):
             nbk = neighbour(bx, by, bz, d)
             if nbk is None or not block_view(fl, *nbk).all():
                 full = False
@@ -369,13 +377,13 @@ def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, group
     slot_of = {k: s for s, k in enumerate(order)}
     nb = len(order)
     coords = np.array(order, np.int32).reshape(nb, 3)
-    nbr = np.full((nb, 18), -1, np.int32)
+    nbr = np.full((nb, q - 1), -1, np.int32)
     fmask = np.zeros(nb, np.uint64)
     for s, (bx, by, bz) in enumerate(order):
-        for d in range(1, 19):
-            q = neighbour(bx, by, bz, d)
-            if q is not None:
-                nbr[s, d - 1] = slot_of[q]
+        for d in range(1, q):
+            nbk = neighbour(bx, by, bz, d)
+            if nbk is not None:
+                nbr[s, d - 1] = slot_of[nbk]
         bits = 0
         v = block_view(fl, bx, by, bz)
         for lz in range(B):
