@@ -112,6 +112,10 @@ typedef struct {
   lbm_storage storage;
   lbm_collision collision;
   lbm_schedule schedule;
+  int32_t lattice;           /* velocity set: 19 (D3Q19, also 0) or 27 (D3Q27, the lattice of
+                                the block-sparse register study); D3Q27 is built for dense
+                                and block-sparse grids with BGK or regularized collision.
+                                Population arrays are [q][N] with q = the lattice. */
 } lbm_grid_desc;
 
 /* Builds the host side of a grid: classification into groups, locality
@@ -177,9 +181,9 @@ lbm_status lbm_read_macroscopic(lbm_grid *g, int32_t level, void *rho_dev, void 
  * (fixed-order two-pass sum). */
 lbm_status lbm_reduce(lbm_grid *g, double *out5_dev, void *stream);
 
-/* Post-collision populations of `level` as FP64 [19][N] in canonical order. */
+/* Post-collision populations of `level` as FP64 [q][N] in canonical order. */
 lbm_status lbm_read_populations(lbm_grid *g, int32_t level, double *f_dev, void *stream);
-/* Overwrites the populations of `level` from FP64 [19][N] canonical order
+/* Overwrites the populations of `level` from FP64 [q][N] canonical order
  * (checkpoint restore); values are rounded to the storage format. */
 lbm_status lbm_write_populations(lbm_grid *g, int32_t level, const double *f_dev, void *stream);
 
@@ -193,8 +197,8 @@ lbm_status lbm_write_populations(lbm_grid *g, int32_t level, const double *f_dev
  *                      blocks pull from some non-fluid source, "full" blocks
  *                      do not
  *   LBM_MAP_COORDS     int32 [nblocks][3]: block coordinates, in storage order
- *   LBM_MAP_NEIGHBOURS int32 [nblocks][18]: slot of the neighbour block in
- *                      direction 1..18, -1 = none
+ *   LBM_MAP_NEIGHBOURS int32 [nblocks][q-1]: slot of the neighbour block in
+ *                      direction 1..q-1 of the grid's lattice, -1 = none
  *   LBM_MAP_FLUIDMASK  uint64 [nblocks]: bit x+4y+16z set for fluid voxels
  *   LBM_MAP_CANONICAL  int64 [nblocks*64]: canonical index of each slot, -1 = not fluid
  *   LBM_MAP_BOUNDARY_BITS uint32 [(nblocks+31)/32]: bit b set if storage block b is a

@@ -14,7 +14,11 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "builder.cpp", "multires_builder.cpp", "step_kernels.hip", "util_kernels.hip", "mlp_kernels.hip"]
+# (source, extra flags): the stepping and utility kernels are compiled once
+# per lattice; the D3Q27 objects carry their symbols in namespace lbm::k27
+SOURCES = [("api.cpp", []), ("builder.cpp", []), ("multires_builder.cpp", []), ("step_kernels.hip", []),
+           ("util_kernels.hip", []), ("mlp_kernels.hip", []),
+           ("step_kernels.hip", ["-DLBM_Q27"]), ("util_kernels.hip", ["-DLBM_Q27"])]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
@@ -23,9 +27,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=
 DEVICE_ONLY = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ_DIR, src + ".o")
-    cmd = [HIPCC, *COMMON, *DEVICE_ONLY, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, extra = job
+    obj = os.path.join(OBJ_DIR, src + ("".join(f.replace("-D", ".") for f in extra)).lower() + ".o")
+    cmd = [HIPCC, *COMMON, *DEVICE_ONLY, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -69,8 +69,27 @@ struct lbm_mlp {
   MlpBuffers B{};
 };
 
+// Lattice-specific launchers (the kernels are compiled once per lattice).
+struct LatticeLaunchers {
+  hipError_t (*one)(const Launch &, int32_t, int32_t, hipStream_t);
+  hipError_t (*init_eq)(const SlotArgs &, const double *, const double *, hipStream_t);
+  hipError_t (*read_macro)(const SlotArgs &, void *, void *, int, hipStream_t);
+  hipError_t (*read_pop)(const SlotArgs &, double *, hipStream_t);
+  hipError_t (*write_pop)(const SlotArgs &, const double *, hipStream_t);
+  hipError_t (*reduce_partial)(const SlotArgs &, double, double *, hipStream_t);
+  hipError_t (*reduce_final)(const double *, int64_t, double *, hipStream_t);
+};
+#define LBM_LAUNCHERS_OF(ns)                                                                          \
+  LatticeLaunchers {                                                                                  \
+    &ns::launch_one, &ns::launch_init_equilibrium, &ns::launch_read_macroscopic,                      \
+        &ns::launch_read_populations, &ns::launch_write_populations, &ns::launch_reduce_partial,      \
+        &ns::launch_reduce_final                                                                      \
+  }
+
 struct lbm_grid {
   lbm_grid_desc desc{};
+  int32_t q = 19;  // lattice
+  LatticeLaunchers ops = LBM_LAUNCHERS_OF(lbm::k19);
   int32_t collision = LBM_BGK;
   const lbm_mlp *mlp = nullptr;
   std::vector<uint8_t> fluid;
@@ -270,6 +289,10 @@ lbm_status lbm_grid_create(const lbm_grid_desc *d, lbm_grid **out) {
     return fail(LBM_ERR_INVALID_ARG, "unknown schedule");
   if (d->schedule == LBM_DISAGG_BITMASK && d->kind == LBM_MULTIRES)
     return fail(LBM_ERR_UNSUPPORTED, "bitmask-based grouping is built for dense and block-sparse grids");
+  if (d->lattice != 0 && d->lattice != 19 && d->lattice != 27)
+    return fail(LBM_ERR_INVALID_ARG, "lattice must be 19 or 27");
+  if (d->lattice == 27 && d->kind == LBM_MULTIRES)
+    return fail(LBM_ERR_UNSUPPORTED, "multires grids are built for D3Q19");
   if (d->kind != LBM_DENSE && d->kind != LBM_BLOCK_SPARSE && d->kind != LBM_MULTIRES)
     return fail(LBM_ERR_INVALID_ARG, "unknown grid kind");
   if (d->kind != LBM_MULTIRES && d->num_levels != 1)
@@ -302,6 +325,10 @@ lbm_status lbm_grid_create(const lbm_grid_desc *d, lbm_grid **out) {
       }
   }
   g->lex = d->kind == LBM_DENSE && d->schedule == LBM_PLAIN_SINGLE_KERNEL;
+  if (d->lattice == 27) {
+    g->q = 27;
+    g->ops = LBM_LAUNCHERS_OF(lbm::k27);
+  }
   if (!g->lex && (d->nx % 4 || d->ny % 4 || d->nz % 4)) {
     delete g;
     return fail(LBM_ERR_INVALID_ARG, "block layouts need box sizes that are multiples of 4");
@@ -357,7 +384,7 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
     g->lv.push_back(r);
   } else if (d.kind != LBM_MULTIRES) {
     std::string e = build_block_level(g->single, d.nx, d.ny, d.nz, d.periodic, g->fluid, g->faces,
-                                      d.kind == LBM_DENSE, nullptr, d.schedule != LBM_DISAGG_BITMASK);
+                                      d.kind == LBM_DENSE, nullptr, d.schedule != LBM_DISAGG_BITMASK, g->q);
     if (!e.empty()) return fail(LBM_ERR_INVALID_ARG, "%s", e.c_str());
     LevelRT r;
     r.L = &g->single;
@@ -392,7 +419,7 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
     }
     for (int k = 0; k < r.nbuf; ++k) {
       r.off_pop[k] = off;
-      off = align256(off + (size_t)r.S * Q * es);
+      off = align256(off + (size_t)r.S * g->q * es);
     }
     if (r.nbuf == 2) r.off_pop[2] = r.off_pop[0];  // the third role is unused
     if (r.L) {
@@ -480,11 +507,11 @@ lbm_status lbm_init_equilibrium(lbm_grid *g, int32_t level, const double *rho, c
   if (lbm_status s = check_level(g, level)) return s;
   LevelRT &r = g->lv[level];
   SlotArgs A = slot_args(g, r);
-  hipError_t e = launch_init_equilibrium(A, rho, u, (hipStream_t)stream);
+  hipError_t e = g->ops.init_eq(A, rho, u, (hipStream_t)stream);
   if (e == hipSuccess && r.nbuf == 3) {
     // the buffer one step back starts equal to the current state
     A.pop_b = pop_ptr(g, r, r.prev);
-    e = launch_init_equilibrium(A, rho, u, (hipStream_t)stream);
+    e = g->ops.init_eq(A, rho, u, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(e, "init_equilibrium");
   g->state = kReady;
@@ -500,7 +527,7 @@ lbm_status lbm_step(lbm_grid *g, int32_t n, void *stream) {
     std::vector<LevelRT> next = g->lv;
     step_launches(g, next, launches);
     for (const Launch &x : launches) {
-      hipError_t e = launch_one(x, g->desc.storage, coll_code(g), (hipStream_t)stream);
+      hipError_t e = g->ops.one(x, g->desc.storage, coll_code(g), (hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "step launch");
     }
     for (size_t l = 0; l < g->lv.size(); ++l) {
@@ -530,7 +557,7 @@ lbm_status lbm_launch_group(lbm_grid *g, int32_t k, void *stream) {
   std::vector<Launch> launches;
   step_launches(g, tmp, launches);
   if (k < 0 || k >= (int32_t)launches.size()) return fail(LBM_ERR_INVALID_ARG, "launch index out of range");
-  hipError_t e = launch_one(launches[k], g->desc.storage, coll_code(g), (hipStream_t)stream);
+  hipError_t e = g->ops.one(launches[k], g->desc.storage, coll_code(g), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "launch_group");
   return LBM_OK;
 }
@@ -539,7 +566,7 @@ lbm_status lbm_read_macroscopic(lbm_grid *g, int32_t level, void *rho, void *u, 
   if (!g || !rho || !u) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
   if (lbm_status s = check_level(g, level)) return s;
-  hipError_t e = launch_read_macroscopic(slot_args(g, g->lv[level]), rho, u, f64 ? 1 : 0, (hipStream_t)stream);
+  hipError_t e = g->ops.read_macro(slot_args(g, g->lv[level]), rho, u, f64 ? 1 : 0, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "read_macroscopic");
   return LBM_OK;
 }
@@ -548,7 +575,7 @@ lbm_status lbm_read_populations(lbm_grid *g, int32_t level, double *f, void *str
   if (!g || !f) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
   if (lbm_status s = check_level(g, level)) return s;
-  hipError_t e = launch_read_populations(slot_args(g, g->lv[level]), f, (hipStream_t)stream);
+  hipError_t e = g->ops.read_pop(slot_args(g, g->lv[level]), f, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "read_populations");
   return LBM_OK;
 }
@@ -561,10 +588,10 @@ lbm_status lbm_write_populations(lbm_grid *g, int32_t level, const double *f, vo
   // slots are written
   LevelRT &r = g->lv[level];
   SlotArgs A = slot_args(g, r);
-  hipError_t e = launch_write_populations(A, f, (hipStream_t)stream);
+  hipError_t e = g->ops.write_pop(A, f, (hipStream_t)stream);
   if (e == hipSuccess && r.nbuf == 3) {
     A.pop_a = pop_ptr(g, r, r.prev);
-    e = launch_write_populations(A, f, (hipStream_t)stream);
+    e = g->ops.write_pop(A, f, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(e, "write_populations");
   g->state = kReady;
@@ -578,10 +605,10 @@ lbm_status lbm_reduce(lbm_grid *g, double *out5, void *stream) {
   hipError_t e = hipSuccess;
   for (size_t l = 0; l < g->lv.size() && e == hipSuccess; ++l) {
     const LevelRT &r = g->lv[l];
-    e = launch_reduce_partial(slot_args(g, r), (double)(1ll << (3 * l)), partial + r.partial_row0 * 5,
+    e = g->ops.reduce_partial(slot_args(g, r), (double)(1ll << (3 * l)), partial + r.partial_row0 * 5,
                               (hipStream_t)stream);
   }
-  if (e == hipSuccess) e = launch_reduce_final(partial, g->partial_rows, out5, (hipStream_t)stream);
+  if (e == hipSuccess) e = g->ops.reduce_final(partial, g->partial_rows, out5, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "reduce");
   return LBM_OK;
 }
@@ -802,8 +829,9 @@ lbm_status lbm_set_collision(lbm_grid *g, lbm_collision c, const lbm_mlp *m) {
   if (c < LBM_BGK || c > LBM_MLP) return fail(LBM_ERR_INVALID_ARG, "unknown collision");
   if (c == LBM_MLP) {
     if (!m || !m->ws) return fail(LBM_ERR_INVALID_ARG, "LBM_MLP needs a bound closure");
-    if (g->lex || g->desc.kind == LBM_MULTIRES || g->desc.schedule != LBM_DISAGG)
-      return fail(LBM_ERR_UNSUPPORTED, "the closure runs on dense or block-sparse grids in the disaggregated schedule");
+    if (g->lex || g->desc.kind == LBM_MULTIRES || g->desc.schedule != LBM_DISAGG || g->q != 19)
+      return fail(LBM_ERR_UNSUPPORTED,
+                  "the closure runs on D3Q19 dense or block-sparse grids in the disaggregated schedule");
     g->mlp = m;
   }
   g->collision = c;
@@ -817,6 +845,7 @@ lbm_status lbm_sample_populations(lbm_grid *g, int32_t level, uint64_t seed, int
   const LevelRT &r = g->lv[level];
   if (!r.L) return fail(LBM_ERR_UNSUPPORTED, "sampling needs a block layout");
   if (!r.L->grouped) return fail(LBM_ERR_UNSUPPORTED, "sampling needs the memory-grouped layout");
+  if (g->q != 19) return fail(LBM_ERR_UNSUPPORTED, "sampling feeds the D3Q19 closure");
   const auto &gc = r.L->group_count;
   const int32_t b0 = (int32_t)(gc[0] + gc[1]), nb = (int32_t)(gc[2] + gc[3]);
   if (nb <= 0) return fail(LBM_ERR_INVALID_ARG, "the level has no non-boundary blocks");

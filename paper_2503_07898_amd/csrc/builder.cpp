@@ -33,7 +33,9 @@ static bool heavy_face(const FaceBC &f) {
 std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
                               const uint8_t periodic[3], const std::vector<uint8_t> &fluid,
                               const FaceBC faces[6], bool dense, const std::vector<uint8_t> *jump,
-                              bool grouped) {
+                              bool grouped, int q) {
+  const LatticeDesc lat = lattice_desc(q);
+  const int NQ = lat.q, NB = lat.q - 1;
   if (!grouped && jump) return "the bitmask layout has no resolution jumps";
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 4 || ny % 4 || nz % 4)
     return "block grids need positive sizes that are multiples of 4";
@@ -67,7 +69,7 @@ std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
   };
   // neighbour block id in lattice direction d, or -1 (outside a non-periodic box)
   auto nb_id = [&](int bx, int by, int bz, int d) -> int64_t {
-    int q[3] = {bx + kCx[d], by + kCy[d], bz + kCz[d]};
+    int q[3] = {bx + lat.cx[d], by + lat.cy[d], bz + lat.cz[d]};
     for (int a = 0; a < 3; ++a) {
       if (q[a] < 0 || q[a] >= nb3[a]) {
         if (!periodic[a]) return -1;
@@ -113,7 +115,7 @@ std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
           g = kGroupBoundary;
         } else {
           bool full = bm[b] == ~0ull;
-          for (int d = 1; d < Q && full; ++d) {
+          for (int d = 1; d < NQ && full; ++d) {
             int64_t n = nb_id(bx, by, bz, d);
             if (n < 0 || bm[n] != ~0ull) full = false;
           }
@@ -153,35 +155,35 @@ std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
   }
 
   L.coords.resize(L.nblocks * 3);
-  L.nbr.assign(L.nblocks * 18, -1);
+  L.nbr.assign(L.nblocks * NB, -1);
   L.fmask.resize(L.nblocks);
-  L.bbm.assign(L.nblocks * 18, 0);
+  L.bbm.assign(L.nblocks * NB, 0);
   for (int64_t s = 0; s < L.nblocks; ++s) {
     int64_t b = order[s];
     int bx = (int)(b % L.nbx), by = (int)((b / L.nbx) % L.nby), bz = (int)(b / ((int64_t)L.nbx * L.nby));
     L.coords[3 * s] = bx; L.coords[3 * s + 1] = by; L.coords[3 * s + 2] = bz;
     L.fmask[s] = bm[b];
-    int64_t nbid[Q];
+    int64_t nbid[27];
     nbid[0] = b;
-    for (int d = 1; d < Q; ++d) {
+    for (int d = 1; d < NQ; ++d) {
       int64_t n = nb_id(bx, by, bz, d);
       nbid[d] = n;
-      if (n >= 0 && L.slot_of_block[n] >= 0) L.nbr[s * 18 + d - 1] = L.slot_of_block[n];
+      if (n >= 0 && L.slot_of_block[n] >= 0) L.nbr[s * NB + d - 1] = L.slot_of_block[n];
     }
     // bounce masks: lane l of direction i pulls from l - c_i
-    for (int i = 1; i < Q; ++i) {
+    for (int i = 1; i < NQ; ++i) {
       uint64_t m = 0;
       for (int l = 0; l < 64; ++l) {
-        int p[3] = {(l & 3) - kCx[i], ((l >> 2) & 3) - kCy[i], (l >> 4) - kCz[i]};
+        int p[3] = {(l & 3) - lat.cx[i], ((l >> 2) & 3) - lat.cy[i], (l >> 4) - lat.cz[i]};
         int o[3];
         for (int a = 0; a < 3; ++a) o[a] = p[a] < 0 ? -1 : (p[a] > 3 ? 1 : 0);
         int64_t src_block = b;
-        if (o[0] || o[1] || o[2]) src_block = nbid[dir_of(o[0], o[1], o[2])];
+        if (o[0] || o[1] || o[2]) src_block = nbid[lat.dir(o[0], o[1], o[2])];
         bool ok = src_block >= 0 &&
                   ((bm[src_block] >> ((p[0] & 3) + 4 * (p[1] & 3) + 16 * (p[2] & 3))) & 1);
         if (!ok) m |= 1ull << l;
       }
-      L.bbm[s * 18 + i - 1] = m;
+      L.bbm[s * NB + i - 1] = m;
     }
   }
 

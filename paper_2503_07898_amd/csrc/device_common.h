@@ -10,6 +10,7 @@
 #include "launch.h"
 
 namespace lbm {
+inline namespace LBM_LATTICE_NS {
 
 // ---------------------------------------------------------------- storage --
 // Populations are stored shifted by the lattice weight.  FP32 keeps h as a
@@ -101,9 +102,23 @@ __device__ __forceinline__ Moments moments(const float (&h)[Q]) {
   float s = h[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i) s = s + h[i];
+#ifndef LBM_Q27
   const float jx = (h[1] - h[2]) + (h[7] - h[8]) + (h[9] - h[10]) + (h[11] - h[12]) + (h[13] - h[14]);
   const float jy = (h[3] - h[4]) + (h[7] - h[8]) + (h[10] - h[9]) + (h[15] - h[16]) + (h[17] - h[18]);
   const float jz = (h[5] - h[6]) + (h[11] - h[12]) + (h[14] - h[13]) + (h[15] - h[16]) + (h[18] - h[17]);
+#else
+  // opposite pairs (i, i+1) for odd i: c_i (h_i - h_i+1)
+  float jx = 0.0f, jy = 0.0f, jz = 0.0f;
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (kOpp[i] > i) {
+      const float d = h[i] - h[kOpp[i]];
+      if constexpr (kCx[i] > 0) jx = jx + d; else if constexpr (kCx[i] < 0) jx = jx - d;
+      if constexpr (kCy[i] > 0) jy = jy + d; else if constexpr (kCy[i] < 0) jy = jy - d;
+      if constexpr (kCz[i] > 0) jz = jz + d; else if constexpr (kCz[i] < 0) jz = jz - d;
+    }
+  });
+#endif
   m.drho = s;
   m.rho = 1.0f + s;
   const float ir = 1.0f / m.rho;
@@ -153,20 +168,28 @@ __device__ __forceinline__ void equilibrium(const Moments &m, float (&heq)[Q]) {
 // Hermite projection of the non-equilibrium part onto second order:
 //   Pi_ab = sum_i c_ia c_ib h_i - drho/3 delta_ab - rho u_a u_b
 //   f1_i  = 4.5 w_i (c_i . Pi . c_i - tr(Pi)/3)
-__device__ __forceinline__ void f1_projection(const float (&h)[Q], const Moments &m, float (&f1)[Q]) {
-  const float p78 = h[7] + h[8], p910 = h[9] + h[10], p1112 = h[11] + h[12];
-  const float p1314 = h[13] + h[14], p1516 = h[15] + h[16], p1718 = h[17] + h[18];
-  const float sxx = (h[1] + h[2]) + p78 + p910 + p1112 + p1314;
-  const float syy = (h[3] + h[4]) + p78 + p910 + p1516 + p1718;
-  const float szz = (h[5] + h[6]) + p1112 + p1314 + p1516 + p1718;
-  const float d3 = m.drho * (1.0f / 3.0f);
-  const float pxx = sxx - d3 - m.rho * m.ux * m.ux;
-  const float pyy = syy - d3 - m.rho * m.uy * m.uy;
-  const float pzz = szz - d3 - m.rho * m.uz * m.uz;
-  const float pxy = (p78 - p910) - m.rho * m.ux * m.uy;
-  const float pxz = (p1112 - p1314) - m.rho * m.ux * m.uz;
-  const float pyz = (p1516 - p1718) - m.rho * m.uy * m.uz;
+__device__ __forceinline__ void hermite2(float pxx, float pyy, float pzz, float pxy, float pxz, float pyz,
+                                         float (&f1)[Q]) {
+  // f1_i = w_i / (2 c_s^4) Q_i : P with Q_i = c_i c_i - I/3
   const float tr3 = (pxx + pyy + pzz) * (1.0f / 3.0f);
+#ifdef LBM_Q27
+  // c_i c_i : P - tr P / 3 for every direction, per opposite pair
+  static_for<0, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (i == 0 || kOpp[i] > i) {
+      constexpr int cx = kCx[i], cy = kCy[i], cz = kCz[i];
+      float q = -tr3;
+      if constexpr (cx != 0) q = q + pxx;
+      if constexpr (cy != 0) q = q + pyy;
+      if constexpr (cz != 0) q = q + pzz;
+      if constexpr (cx * cy != 0) q = fmaf((float)(2 * cx * cy), pxy, q);
+      if constexpr (cx * cz != 0) q = fmaf((float)(2 * cx * cz), pxz, q);
+      if constexpr (cy * cz != 0) q = fmaf((float)(2 * cy * cz), pyz, q);
+      f1[i] = (4.5f * weight_f(i)) * q;
+      if constexpr (i != 0) f1[kOpp[i]] = f1[i];
+    }
+  });
+#else
   const float k1 = 4.5f * weight_f(1), k2 = 4.5f * weight_f(7);
   f1[0] = 4.5f * weight_f(0) * -tr3;
   f1[1] = f1[2] = k1 * (pxx - tr3);
@@ -179,6 +202,44 @@ __device__ __forceinline__ void f1_projection(const float (&h)[Q], const Moments
   f1[13] = f1[14] = k2 * (exz - 2.0f * pxz);
   f1[15] = f1[16] = k2 * (eyz + 2.0f * pyz);
   f1[17] = f1[18] = k2 * (eyz - 2.0f * pyz);
+#endif
+}
+
+__device__ __forceinline__ void f1_projection(const float (&h)[Q], const Moments &m, float (&f1)[Q]) {
+#ifdef LBM_Q27
+  // second moments of h over opposite pairs (c c is even in c)
+  float sxx = 0.0f, syy = 0.0f, szz = 0.0f, sxy = 0.0f, sxz = 0.0f, syz = 0.0f;
+  static_for<1, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (kOpp[i] > i) {
+      constexpr int cx = kCx[i], cy = kCy[i], cz = kCz[i];
+      const float p = h[i] + h[kOpp[i]];
+      if constexpr (cx != 0) sxx = sxx + p;
+      if constexpr (cy != 0) syy = syy + p;
+      if constexpr (cz != 0) szz = szz + p;
+      if constexpr (cx * cy > 0) sxy = sxy + p; else if constexpr (cx * cy < 0) sxy = sxy - p;
+      if constexpr (cx * cz > 0) sxz = sxz + p; else if constexpr (cx * cz < 0) sxz = sxz - p;
+      if constexpr (cy * cz > 0) syz = syz + p; else if constexpr (cy * cz < 0) syz = syz - p;
+    }
+  });
+  const float d3 = m.drho * (1.0f / 3.0f);
+  hermite2(sxx - d3 - m.rho * m.ux * m.ux, syy - d3 - m.rho * m.uy * m.uy, szz - d3 - m.rho * m.uz * m.uz,
+           sxy - m.rho * m.ux * m.uy, sxz - m.rho * m.ux * m.uz, syz - m.rho * m.uy * m.uz, f1);
+#else
+  const float p78 = h[7] + h[8], p910 = h[9] + h[10], p1112 = h[11] + h[12];
+  const float p1314 = h[13] + h[14], p1516 = h[15] + h[16], p1718 = h[17] + h[18];
+  const float sxx = (h[1] + h[2]) + p78 + p910 + p1112 + p1314;
+  const float syy = (h[3] + h[4]) + p78 + p910 + p1516 + p1718;
+  const float szz = (h[5] + h[6]) + p1112 + p1314 + p1516 + p1718;
+  const float d3 = m.drho * (1.0f / 3.0f);
+  const float pxx = sxx - d3 - m.rho * m.ux * m.ux;
+  const float pyy = syy - d3 - m.rho * m.uy * m.uy;
+  const float pzz = szz - d3 - m.rho * m.uz * m.uz;
+  const float pxy = (p78 - p910) - m.rho * m.ux * m.uy;
+  const float pxz = (p1112 - p1314) - m.rho * m.ux * m.uz;
+  const float pyz = (p1516 - p1718) - m.rho * m.uy * m.uz;
+  hermite2(pxx, pyy, pzz, pxy, pxz, pyz, f1);
+#endif
 }
 
 enum : int { kCollBGK = 0, kCollRegularized = 1, kCollMLP = 2 };
@@ -348,4 +409,5 @@ __device__ __forceinline__ int xcd_remap(int k, int nwg) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
+}  // inline namespace
 }  // namespace lbm

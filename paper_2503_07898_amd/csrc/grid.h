@@ -34,9 +34,9 @@ struct BlockLevel {
   int64_t nblocks = 0;
   std::array<int64_t, kNumGroups> group_count{};
   std::vector<int32_t> coords;     // [nblocks][3]
-  std::vector<int32_t> nbr;        // [nblocks][18]
+  std::vector<int32_t> nbr;        // [nblocks][q-1] (D3Q19: face and edge blocks; D3Q27: + corners)
   std::vector<uint64_t> fmask;     // [nblocks]
-  std::vector<uint64_t> bbm;       // [nblocks][18]: lanes whose source is not a fluid voxel
+  std::vector<uint64_t> bbm;       // [nblocks][q-1]: lanes whose source is not a fluid voxel
   std::vector<int32_t> canon;      // [nblocks*64]: canonical index or -1
   std::vector<int32_t> slot_of_block;  // [nbz][nby][nbx] -> block slot or -1
   int64_t n_fluid = 0;
@@ -59,10 +59,12 @@ uint64_t morton_key(uint32_t bx, uint32_t by, uint32_t bz);
 // jump; blocks holding one form the first group.
 // `grouped` = false keeps all blocks in one Morton order (bitmask-based
 // grouping) and builds the per-voxel indirect ids and boundary records.
+// `q` selects the lattice (19 or 27), which fixes the neighbour directions.
 std::string build_block_level(BlockLevel &L, int32_t nx, int32_t ny, int32_t nz,
                               const uint8_t periodic[3], const std::vector<uint8_t> &fluid,
                               const FaceBC faces[6], bool dense,
-                              const std::vector<uint8_t> *jump = nullptr, bool grouped = true);
+                              const std::vector<uint8_t> *jump = nullptr, bool grouped = true,
+                              int q = 19);
 
 // ---------------------------------------------------------------- multires
 // Source-list entry of the jump tables: bits 31..29 buffer tag, bit 28 use

@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "../../include/lbm.h"
+#include "lattice.h"
 
 namespace lbm {
 
@@ -20,8 +21,8 @@ struct StepArgs {
   const void *src;           // [19][S] populations read (post-collision of the last step)
   void *dst;                 // [19][S] populations written
   uint32_t S;                // plane stride in slots
-  const int32_t *nbr;        // [nblocks][18] neighbour block slots (-1 = none)
-  const uint64_t *bbm;       // [nblocks][18] bounce masks
+  const int32_t *nbr;        // [nblocks][Q-1] neighbour block slots (-1 = none)
+  const uint64_t *bbm;       // [nblocks][Q-1] bounce masks
   const int32_t *coords;     // [nblocks] packed bx | by << 10 | bz << 20
   int32_t nx, ny, nz;        // box in voxels
   float omega;               // 1 / tau
@@ -68,8 +69,6 @@ struct Launch {
   MrArgs mr;
 };
 
-hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipStream_t s);
-
 // ---- learned closure: training and utility launches (mlp_kernels.hip) ----
 struct MlpBuffers {
   float *params;      // [kMlpParams] FP32 master weights
@@ -88,6 +87,7 @@ struct MlpBuffers {
   int64_t batch_max;
 };
 
+namespace k19 {  // D3Q19 only
 hipError_t mlp_pack(const MlpBuffers &B, hipStream_t s);
 hipError_t mlp_fit_standardization(const MlpBuffers &B, const float *f, int64_t n, hipStream_t s);
 hipError_t mlp_forward(const MlpBuffers &B, const float *f, int64_t n, float *y, hipStream_t s);
@@ -96,6 +96,7 @@ hipError_t mlp_gradients(const MlpBuffers &B, const float *f, const int64_t *idx
 hipError_t mlp_adam(const MlpBuffers &B, float lr, int32_t t, hipStream_t s);
 hipError_t launch_sample_pre(const StepArgs &a, int32_t storage, int32_t b0, int32_t nb, uint64_t seed, int64_t n,
                              float *out, hipStream_t s);
+}  // namespace k19
 
 // Utility kernels over a slot range [0, nslots) with an optional canonical
 // map (NULL = identity, every slot fluid).
@@ -109,15 +110,24 @@ struct SlotArgs {
   int32_t storage;
 };
 
-hipError_t launch_init_equilibrium(const SlotArgs &A, const double *rho, const double *u,
-                                   hipStream_t s);
-hipError_t launch_read_macroscopic(const SlotArgs &A, void *rho, void *u, int out_f64,
-                                   hipStream_t s);
-hipError_t launch_read_populations(const SlotArgs &A, double *f, hipStream_t s);
-hipError_t launch_write_populations(const SlotArgs &A, const double *f, hipStream_t s);
-// partial sums per 64-slot group (weighted by `weight`) into partial[first_row..]
-hipError_t launch_reduce_partial(const SlotArgs &A, double weight, double *partial,
-                                 hipStream_t s);
-hipError_t launch_reduce_final(const double *partial, int64_t rows, double *out5, hipStream_t s);
+// Launchers built once per lattice (step_kernels.hip and util_kernels.hip
+// are compiled for D3Q19 into k19 and for D3Q27 into k27).
+#define LBM_DECLARE_LATTICE_LAUNCHERS                                                                  \
+  hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipStream_t s);           \
+  hipError_t launch_init_equilibrium(const SlotArgs &A, const double *rho, const double *u,             \
+                                     hipStream_t s);                                                   \
+  hipError_t launch_read_macroscopic(const SlotArgs &A, void *rho, void *u, int out_f64, hipStream_t s); \
+  hipError_t launch_read_populations(const SlotArgs &A, double *f, hipStream_t s);                      \
+  hipError_t launch_write_populations(const SlotArgs &A, const double *f, hipStream_t s);               \
+  /* partial sums per 64-slot group (weighted by `weight`) into partial[first_row..] */                 \
+  hipError_t launch_reduce_partial(const SlotArgs &A, double weight, double *partial, hipStream_t s);   \
+  hipError_t launch_reduce_final(const double *partial, int64_t rows, double *out5, hipStream_t s);
+
+namespace k19 {
+LBM_DECLARE_LATTICE_LAUNCHERS
+}
+namespace k27 {
+LBM_DECLARE_LATTICE_LAUNCHERS
+}
 
 }  // namespace lbm

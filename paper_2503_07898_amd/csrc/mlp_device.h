@@ -1,20 +1,25 @@
 // Device side of the learned collision closure: a 19-64-64-19 perceptron
 // evaluated per wave of 64 voxels with bfloat16 matrix-core instructions
 // (v_mfma_f32_32x32x16_bf16, FP32 accumulation), tanh-form GELU, and the
-// projection that removes mass and momentum from its output.
+// projection of its output onto the second-order Hermite space.
 //
 // Per wave, layer k computes Z[64 voxels x N] = A[64 x K] W[K x N] + b as
 // 2 (voxel tiles) x N/32 (column tiles) x K/16 (k chunks) MFMAs.  Activations
 // go through the wave's own LDS region (bf16, padded rows); weights sit in
 // LDS in operand order, shared by the workgroup.
 #pragma once
+#ifdef LBM_Q27
+#error "the closure network is a D3Q19 network"
+#endif
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
+#include "device_common.h"
 #include "lattice.h"
 
 namespace lbm {
+inline namespace LBM_LATTICE_NS {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
@@ -184,19 +189,23 @@ __device__ __forceinline__ void stage_weights(__bf16 *wl, const __bf16 *wg) {
   __syncthreads();
 }
 
-// P(y)_i = y_i - w_i sum_j y_j - 3 w_i c_i . sum_j c_j y_j
+// Second-order Hermite projection, P(y)_i = w_i/(2 c_s^4) Q_i : sum_j Q_j y_j:
+// keeps the stress-like part of y and drops mass, momentum and every
+// higher (ghost) moment.
 __device__ __forceinline__ void project_out(float (&y)[Q]) {
   float s = y[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i) s = s + y[i];
-  const float jx = (y[1] - y[2]) + (y[7] - y[8]) + (y[9] - y[10]) + (y[11] - y[12]) + (y[13] - y[14]);
-  const float jy = (y[3] - y[4]) + (y[7] - y[8]) + (y[10] - y[9]) + (y[15] - y[16]) + (y[17] - y[18]);
-  const float jz = (y[5] - y[6]) + (y[11] - y[12]) + (y[14] - y[13]) + (y[15] - y[16]) + (y[18] - y[17]);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float cj = (float)kCx[i] * jx + (float)kCy[i] * jy + (float)kCz[i] * jz;
-    y[i] = y[i] - weight_f(i) * fmaf(3.0f, cj, s);
-  }
+  const float p78 = y[7] + y[8], p910 = y[9] + y[10], p1112 = y[11] + y[12];
+  const float p1314 = y[13] + y[14], p1516 = y[15] + y[16], p1718 = y[17] + y[18];
+  const float s3 = s * (1.0f / 3.0f);
+  const float pxx = (y[1] + y[2]) + p78 + p910 + p1112 + p1314 - s3;
+  const float pyy = (y[3] + y[4]) + p78 + p910 + p1516 + p1718 - s3;
+  const float pzz = (y[5] + y[6]) + p1112 + p1314 + p1516 + p1718 - s3;
+  // the off-diagonal sums pair opposite directions (c_a c_b is even in c)
+  const float pxy = p78 - p910, pxz = p1112 - p1314, pyz = p1516 - p1718;
+  hermite2(pxx, pyy, pzz, pxy, pxz, pyz, y);
 }
 
+}  // inline namespace
 }  // namespace lbm

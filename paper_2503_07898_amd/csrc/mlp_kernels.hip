@@ -19,6 +19,7 @@
 #include "mlp_device.h"
 
 namespace lbm {
+inline namespace LBM_LATTICE_NS {
 
 namespace {
 
@@ -97,24 +98,19 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *f, const int64_t *
   }
   e = e / (double)s2_of(stdz);
   // loss = mean d^2 / s2 with s2 the mean target variance (scale-free loss);
-  // dL/dP = 2 d / (n 19 s2); dL/dy = dL/dP * M, M_ij = delta_ij - w_i - 3 w_i c_i.c_j
+  // dL/dP = 2 d / (n 19 s2).  With P = M y, M_ij = w_i (Q_i : Q_j) / (2 c_s^4),
+  // dL/dy_j = sum_i dL/dP_i M_ij = P(w o dL/dP)_j / w_j.
   const float s2 = s2_of(stdz);
   const float sc = 2.0f / ((float)(n * Q) * s2);
-  float sw = 0.0f, swx = 0.0f, swy = 0.0f, swz = 0.0f;
+  float z[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float g = d[i] * sc * weight_f(i);
-    sw += g;
-    swx += (float)kCx[i] * g;
-    swy += (float)kCy[i] * g;
-    swz += (float)kCz[i] * g;
-  }
+  for (int i = 0; i < Q; ++i) z[i] = d[i] * sc * weight_f(i);
+  project_out(z);
   if (valid)
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const float cdot = (float)kCx[i] * swx + (float)kCy[i] * swy + (float)kCz[i] * swz;
-      const float dy = d[i] * sc - sw - 3.0f * cdot;
-      dyt[k * Q + i] = dy * stdz[64 + i];
+      const float inv_w = i == 0 ? 3.0f : (i < 7 ? 18.0f : 36.0f);
+      dyt[k * Q + i] = z[i] * inv_w * stdz[64 + i];
     }
   for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
   if (lane == 0 && partial) partial[blockIdx.x * 4 + wave] = e;
@@ -322,4 +318,5 @@ hipError_t mlp_adam(const MlpBuffers &B, float lr, int32_t t, hipStream_t s) {
   return mlp_pack(B, s);
 }
 
+}  // inline namespace
 }  // namespace lbm

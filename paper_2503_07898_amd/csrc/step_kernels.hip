@@ -25,15 +25,18 @@
 
 #include "device_common.h"
 #include "launch.h"
+#ifndef LBM_Q27
 #include "mlp_device.h"
+#endif
 
 namespace lbm {
+inline namespace LBM_LATTICE_NS {
 
 // Slot of the source of lane `lane` in direction I (pull from x - c_I).
-// Uniform neighbour slots nbv[d-1] for lattice directions d = 1..18; the
+// Uniform neighbour slots nbv[d-1] for lattice directions d = 1..Q-1; the
 // source block is chosen per lane by which block faces the pull crosses.
 template <int I>
-__device__ __forceinline__ uint32_t pull_slot(int lane, int own, const int32_t (&nbv)[18]) {
+__device__ __forceinline__ uint32_t pull_slot(int lane, int own, const int32_t (&nbv)[kNbr]) {
   constexpr int cx = kCx[I], cy = kCy[I], cz = kCz[I];
   const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
   const bool ox = cx != 0 && lx == (cx > 0 ? 0 : 3);
@@ -46,6 +49,7 @@ __device__ __forceinline__ uint32_t pull_slot(int lane, int own, const int32_t (
   if constexpr (cx != 0 && cy != 0) b = (ox && oy) ? nbv[dir_of(-cx, -cy, 0) - 1] : b;
   if constexpr (cx != 0 && cz != 0) b = (ox && oz) ? nbv[dir_of(-cx, 0, -cz) - 1] : b;
   if constexpr (cy != 0 && cz != 0) b = (oy && oz) ? nbv[dir_of(0, -cy, -cz) - 1] : b;
+  if constexpr (cx != 0 && cy != 0 && cz != 0) b = (ox && oy && oz) ? nbv[dir_of(-cx, -cy, -cz) - 1] : b;
   const int local = ((lx - cx) & 3) | (((ly - cy) & 3) << 2) | (((lz - cz) & 3) << 4);
   return (uint32_t)(b * 64 + local);
 }
@@ -67,13 +71,13 @@ __device__ __forceinline__ void interior_block(const StepArgs &a, int b) {
   const uint32_t S = a.S;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
 
-  int32_t nbv[18];
+  int32_t nbv[kNbr];
 #pragma unroll
-  for (int d = 0; d < 18; ++d) nbv[d] = a.nbr[(size_t)b * 18 + d];
-  uint64_t bm[18];
+  for (int d = 0; d < kNbr; ++d) nbv[d] = a.nbr[(size_t)b * kNbr + d];
+  uint64_t bm[kNbr];
   if constexpr (MASKED) {
 #pragma unroll
-    for (int d = 0; d < 18; ++d) bm[d] = a.bbm[(size_t)b * 18 + d];
+    for (int d = 0; d < kNbr; ++d) bm[d] = a.bbm[(size_t)b * kNbr + d];
   }
 
   float h[Q];
@@ -117,6 +121,7 @@ __global__ __launch_bounds__(256) void k_block_interior_bits(StepArgs a, int32_t
   interior_block<ST, COLL, true, true>(a, b);
 }
 
+#ifndef LBM_Q27  // D3Q19 only
 // ------------------------------------------ interior kernel, learned closure --
 // Same gather as k_block_interior; the collision evaluates the closure
 // network for the wave's 64 voxels on the matrix cores, projects its output
@@ -138,13 +143,13 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
   T *__restrict__ dst = (T *)a.dst;
   const uint32_t S = a.S;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
-  int32_t nbv[18];
+  int32_t nbv[kNbr];
 #pragma unroll
-  for (int d = 0; d < 18; ++d) nbv[d] = a.nbr[(size_t)b * 18 + d];
-  uint64_t bm[18];
+  for (int d = 0; d < kNbr; ++d) nbv[d] = a.nbr[(size_t)b * kNbr + d];
+  uint64_t bm[kNbr];
   if constexpr (MASKED) {
 #pragma unroll
-    for (int d = 0; d < 18; ++d) bm[d] = a.bbm[(size_t)b * 18 + d];
+    for (int d = 0; d < kNbr; ++d) bm[d] = a.bbm[(size_t)b * kNbr + d];
   }
   float h[Q];
   h[0] = ST::load(src, own_slot);
@@ -200,6 +205,8 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
 }
 
+#endif  // LBM_Q27
+
 // ------------------------------------------------------ boundary kernel --
 // Per-block body of the boundary kernels.  REC: boundary values from the
 // voxel's indirect record (bitmask layout) instead of the face table.
@@ -212,12 +219,12 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, int b) {
   const uint32_t S = a.S;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
 
-  int32_t nbv[18];
-  uint64_t bm[18];
+  int32_t nbv[kNbr];
+  uint64_t bm[kNbr];
 #pragma unroll
-  for (int d = 0; d < 18; ++d) {
-    nbv[d] = a.nbr[(size_t)b * 18 + d];
-    bm[d] = a.bbm[(size_t)b * 18 + d];
+  for (int d = 0; d < kNbr; ++d) {
+    nbv[d] = a.nbr[(size_t)b * kNbr + d];
+    bm[d] = a.bbm[(size_t)b * kNbr + d];
   }
   const int packed = a.coords[b];
   const int gx = (packed & 1023) * 4 + (lane & 3);
@@ -324,6 +331,7 @@ __global__ __launch_bounds__(256) void k_block_collide(StepArgs a, int32_t g0, i
   for (int i = 0; i < Q; ++i) ST::store(buf + (size_t)i * S, own_slot, h[i]);
 }
 
+#ifndef LBM_Q27  // D3Q19 only
 // ----------------------------------------------- multires jump kernel ---
 // Blocks next to a resolution jump.  Each (voxel, direction) has one table
 // entry per substep phase: a tagged slot in one of five buffers, or a list
@@ -375,6 +383,8 @@ __global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * a.S, own_slot, h[i]);
 }
 
+#endif  // LBM_Q27
+
 // ---------------------------------------------- dense lexicographic arm ---
 // One thread per voxel of an all-fluid box stored as [19][nx*ny*nz] with
 // x fastest; face rules evaluated inline for every voxel.
@@ -424,6 +434,7 @@ __global__ __launch_bounds__(256) void k_lex(StepArgs a) {
   for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own, h[i]);
 }
 
+#ifndef LBM_Q27  // D3Q19 only
 // ------------------------------------------------------ training sampler --
 // splitmix64 (Steele, Lea and Flood 2014), a counter-based generator.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -452,15 +463,15 @@ __global__ void k_sample_pre(StepArgs a, int32_t b0, int32_t nb, uint64_t seed, 
     if ((a.fmask[bb] >> ll) & 1ull) break;
   }
   const T *src = (const T *)a.src;
-  int32_t nbv[18];
-  for (int d = 0; d < 18; ++d) nbv[d] = a.nbr[(size_t)b * 18 + d];
+  int32_t nbv[kNbr];
+  for (int d = 0; d < kNbr; ++d) nbv[d] = a.nbr[(size_t)b * kNbr + d];
   const uint32_t own = (uint32_t)b * 64u + (uint32_t)lane;
   out[k * Q] = weight_f(0) + ST::load(src, own);
   static_for<1, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     uint32_t slot = pull_slot<i>(lane, b, nbv);
     uint32_t plane = i;
-    if ((a.bbm[(size_t)b * 18 + i - 1] >> lane) & 1ull) {
+    if ((a.bbm[(size_t)b * kNbr + i - 1] >> lane) & 1ull) {
       slot = own;
       plane = kOpp[i];
     }
@@ -480,6 +491,8 @@ hipError_t launch_sample_pre(const StepArgs &a, int32_t storage, int32_t b0, int
   }
   return hipGetLastError();
 }
+
+#endif  // LBM_Q27
 
 // --------------------------------------------------------------- launch --
 template <class ST, int COLL>
@@ -507,10 +520,12 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
       if (f) hipLaunchKernelGGL((k_block_boundary<ST, COLL, true>), grd, blk, 0, s, L.args, g0, n);
       else hipLaunchKernelGGL((k_block_boundary<ST, COLL, false>), grd, blk, 0, s, L.args, g0, n);
       break;
+#ifndef LBM_Q27
     case kKernelJump:
       if (f) hipLaunchKernelGGL((k_mr_jump<ST, COLL, true>), grd, blk, 0, s, L.args, L.mr, g0, n);
       else hipLaunchKernelGGL((k_mr_jump<ST, COLL, false>), grd, blk, 0, s, L.args, L.mr, g0, n);
       break;
+#endif
     case kKernelCollide:
       hipLaunchKernelGGL((k_block_collide<ST, COLL, false>), grd, blk, 0, s, L.args, g0, n);
       break;
@@ -529,6 +544,7 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
+#ifndef LBM_Q27
 template <class ST>
 static hipError_t launch_mlp(const Launch &L, hipStream_t s) {
   const int32_t g0 = L.first, n = L.count;
@@ -538,9 +554,13 @@ static hipError_t launch_mlp(const Launch &L, hipStream_t s) {
   else hipLaunchKernelGGL((k_block_interior_mlp<ST, true>), grd, blk, 0, s, L.args, g0, n);
   return hipGetLastError();
 }
+#endif
 
 hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipStream_t s) {
   if (collision == kCollMLP) {
+#ifdef LBM_Q27
+    return hipErrorInvalidValue;  // the closure is a D3Q19 network
+#else
     // the closure runs on the non-boundary groups; every other kernel uses
     // the regularized operator it was trained to imitate
     if (L.fused && (L.kind == kKernelFull || L.kind == kKernelMasked)) {
@@ -552,6 +572,7 @@ hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipSt
       return hipErrorInvalidValue;
     }
     collision = kCollRegularized;
+#endif
   }
   const bool reg = collision == kCollRegularized;
   switch (storage) {
@@ -562,4 +583,5 @@ hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipSt
   return hipErrorInvalidValue;
 }
 
+}  // inline namespace
 }  // namespace lbm

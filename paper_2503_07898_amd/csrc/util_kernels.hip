@@ -8,6 +8,7 @@
 #include "launch.h"
 
 namespace lbm {
+inline namespace LBM_LATTICE_NS {
 
 __device__ __forceinline__ int64_t canon_of(const SlotArgs &A, int64_t slot) {
   return A.canon ? (int64_t)A.canon[slot] : slot;
@@ -189,4 +190,5 @@ hipError_t launch_reduce_final(const double *partial, int64_t rows, double *out5
   return hipGetLastError();
 }
 
+}  // inline namespace
 }  // namespace lbm

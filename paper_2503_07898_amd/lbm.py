@@ -47,6 +47,7 @@ class GridDesc(ctypes.Structure):
         ("storage", ctypes.c_int32),
         ("collision", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
+        ("lattice", ctypes.c_int32),
     ]
 
 
@@ -293,6 +294,7 @@ class Grid:
     device: str = "cuda"
     level_map: np.ndarray | None = None
     levels: int = 1
+    q: int = 19  # lattice: D3Q19 or D3Q27
 
     def __post_init__(self):
         d = GridDesc()
@@ -313,6 +315,7 @@ class Grid:
             d.fluid_mask = self._mask.ctypes.data
         d.tau = float(self.tau)
         d.storage, d.collision, d.schedule = self.storage, self.collision, self.schedule
+        d.lattice = self.q
         self.h = lbm_grid_create(d)
         for face, (k, val) in self.faces.items():
             lbm_set_boundary(self.h, face, k, val)
@@ -356,14 +359,14 @@ class Grid:
 
     def populations(self, level: int = 0):
         import torch
-        f = torch.empty(19, self.n_level(level), dtype=torch.float64, device=self.device)
+        f = torch.empty(self.q, self.n_level(level), dtype=torch.float64, device=self.device)
         lbm_read_populations(self.h, level, f.data_ptr())
         return f
 
     def write_populations(self, f, level: int = 0):
         import torch
         n = self.n_level(level)
-        t = torch.as_tensor(f, dtype=torch.float64).reshape(19, n).contiguous().to(self.device)
+        t = torch.as_tensor(f, dtype=torch.float64).reshape(self.q, n).contiguous().to(self.device)
         lbm_write_populations(self.h, level, t.data_ptr())
         torch.cuda.current_stream().synchronize()
 

@@ -236,3 +236,34 @@ def test_launch_structure_bitmask_grouping():
     with pytest.raises(lbm.LbmError):
         lbm.Grid(*n, schedule=lbm.DISAGG_BITMASK, kind=lbm.MULTIRES, levels=2,
                  level_map=np.zeros(n[::-1], np.uint8), device="cpu")
+
+
+@pytest.mark.parametrize("case", [0, 1, 4])
+@pytest.mark.parametrize("grouped", [True, False])
+def test_index_maps_d3q27(orc, case, grouped):
+    """D3Q27 layouts: 26 neighbour blocks per block (corners included), maps
+    equal to the reference builder's for the same lattice."""
+    n, periodic, kinds, dense = CASES[case]
+    fluid = None if dense else workloads.random_mask(*n, seed=40 + case, solid_fraction=0.15,
+                                                     empty_block_fraction=0.25)
+    g = lbm.Grid(*n, kind=lbm.DENSE if dense else lbm.BLOCK_SPARSE, periodic=periodic, fluid=fluid,
+                 faces=_faces(periodic, kinds), q=27, device="cpu",
+                 schedule=lbm.DISAGG if grouped else lbm.DISAGG_BITMASK)
+    okinds = [{"bb": orc.BB, "moving": orc.MOVING, "vel": orc.REG_VEL, "pres": orc.REG_PRES}[k]
+              for k in kinds]
+    ref = orc.build_block_maps(*n, periodic, fluid, okinds, dense, grouped=grouped, q=27)
+    groups = g.index_map(lbm.MAP_GROUPS)
+    assert tuple(groups[1:4]) == ref["groups"]
+    nb = int(groups[4])
+    assert np.array_equal(g.index_map(lbm.MAP_COORDS).reshape(nb, 3), ref["coords"])
+    assert np.array_equal(g.index_map(lbm.MAP_NEIGHBOURS).reshape(nb, 26), ref["nbr"])
+    assert np.array_equal(g.index_map(lbm.MAP_CANONICAL), ref["canon"])
+    g.close()
+
+
+def test_d3q27_restrictions():
+    with pytest.raises(lbm.LbmError):
+        lbm.Grid(32, 32, 32, kind=lbm.MULTIRES, levels=2, level_map=np.zeros((32, 32, 32), np.uint8),
+                 q=27, device="cpu")
+    with pytest.raises(lbm.LbmError):
+        lbm.Grid(8, 8, 8, q=23, device="cpu")
