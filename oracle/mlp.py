@@ -20,7 +20,13 @@ content, and the post-collision state is f* = f^eq + (1 - 1/tau) rho P(y).
 only removed mass and momentum let ghost content through, which near
 tau = 1/2 is relaxed with a factor close to -1 and grew in closed loop.)  A voxel
 falls back to the regularized operator if any standardized input exceeds 8
-in magnitude or any output population is negative.  Training minimizes the
+in magnitude, if any output population is negative, or -- the regularized
+operator acting as judge of the closure's error -- if
+|P(y) - f1/rho|_2 > judge |f1/rho|_2 (judge = 0.01 by default; 0 disables
+the test).  Near tau = 1/2 the non-equilibrium part is relaxed by a factor
+close to -1, and a closure that overshoots the regularized stress by more
+than about 1/(1 - 1/tau) - 1 (1.5% at tau = 0.5038) makes that factor
+exceed 1 in magnitude; the judge keeps every accepted update inside it.  Training minimizes the
 mean squared error between P(y) and f1/rho, divided by the mean target
 variance (mean of out_std^2) so that the loss is scale free, with Adam.
 """
@@ -38,6 +44,7 @@ A_GELU = 0.044715
 HIDDEN = 64
 Q = 19
 FALLBACK_LIMIT = 8.0
+JUDGE = 0.01
 
 
 def gelu(x):
@@ -188,7 +195,7 @@ def closure_inputs(f):
     return out
 
 
-def collide(p: Params, f, tau, y_override=None):
+def collide(p: Params, f, tau, y_override=None, judge: float = JUDGE):
     """Post-collision populations of the closure for f (N, 19); returns
     (f*, fell_back (N,) bool).  y_override replaces the network output
     (used to check the assembly against the regularized operator)."""
@@ -196,6 +203,7 @@ def collide(p: Params, f, tau, y_override=None):
     g = closure_inputs(f)
     y = forward(p, g) if y_override is None else np.asarray(y_override, np.float64)
     py = project(y)
+    t = regularized_target(f)
     out = np.zeros_like(f)
     fell = np.zeros(f.shape[0], bool)
     x = (g - p.in_mean) / p.in_std
@@ -203,7 +211,8 @@ def collide(p: Params, f, tau, y_override=None):
         rho, u = _orc.moments(f[k])
         feq = _orc.equilibrium(rho, u)
         fs = feq + (1.0 - 1.0 / tau) * rho * py[k]
-        if np.any(np.abs(x[k]) > FALLBACK_LIMIT) or np.any(fs < 0):
+        off = judge > 0 and np.sum((py[k] - t[k]) ** 2) > judge * judge * np.sum(t[k] ** 2)
+        if np.any(np.abs(x[k]) > FALLBACK_LIMIT) or np.any(fs < 0) or off:
             fs = _orc.collide_regularized(f[k], tau)
             fell[k] = True
         out[k] = fs

@@ -137,3 +137,20 @@ def test_bf16_rounding_reference(mlp):
     assert out[2] == 1.0 + 2 ** -6          # tie -> even (up)
     assert out[3] == -2.5
     assert out[4] == 3.140625
+
+
+def test_closure_judge_threshold(orc, mlp):
+    """The regularized operator judges the closure: an output within 1% (L2)
+    of its non-equilibrium part is accepted, one 2% off falls back, and
+    judge = 0 accepts both."""
+    p = make_params(mlp)
+    p.in_std[:] = 1e3  # inputs far inside the range limit
+    f = sample_populations(orc, 10, 6)
+    t = mlp.regularized_target(f)
+    for scale, judge, expect_fall in ((1.005, 0.01, False), (1.02, 0.01, True), (1.02, 0.0, False)):
+        out, fell = mlp.collide(p, f, 0.51, y_override=t * scale, judge=judge)
+        assert (fell == expect_fall).all(), (scale, judge)
+        if not expect_fall:
+            rho = f.sum(-1)
+            feq = np.array([orc.equilibrium(*orc.moments(fk)) for fk in f])
+            assert np.allclose(out, feq + (1 - 1 / 0.51) * rho[:, None] * t * scale, atol=1e-15, rtol=0)
