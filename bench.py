@@ -36,67 +36,33 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS and % of HBM roofline, FP32 plain vs FP16-storage vs MLP closure"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {0: 152, 1: 76, 2: 76}  # FP32, FP16-shifted, BF16-shifted
+# closure network per update on the matrix cores: 2 x (32x64 + 64x64 + 64x32)
+# multiply-adds with the 19-wide layers padded to 32
+MLP_MFMA_FLOPS = 2 * (32 * 64 + 64 * 64 + 64 * 32)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def cavity(lbm, n=256, storage=0, schedule=1, tau=0.55, uw=0.1):
-    faces = {f: (lbm.BC_BOUNCE_BACK, (0, 0, 0)) for f in range(6)}
-    faces[lbm.ZMAX] = (lbm.BC_MOVING_WALL, (uw, 0.0, 0.0))
-    g = lbm.Grid(n, n, n, kind=lbm.DENSE, periodic=(False,) * 3, faces=faces, tau=tau,
-                 storage=storage, schedule=schedule).bind()
-    N = g.n
-    g.init_equilibrium(np.ones(N), np.zeros((3, N)))
-    return g
-
-
-def tunnel(lbm, workloads, storage=0, schedule=1, tau=0.6, n=(512, 256, 256)):
-    fluid, _ = workloads.sphere_packing(*n, seed=7898)
-    faces = {lbm.XMIN: (lbm.BC_REG_VELOCITY, (0.05, 0.0, 0.0)),
-             lbm.XMAX: (lbm.BC_REG_PRESSURE, (1.0, 0.0, 0.0))}
-    for f in (lbm.YMIN, lbm.YMAX, lbm.ZMIN, lbm.ZMAX):
-        faces[f] = (lbm.BC_BOUNCE_BACK, (0, 0, 0))
-    g = lbm.Grid(*n, kind=lbm.BLOCK_SPARSE, periodic=(False,) * 3, fluid=fluid, faces=faces,
-                 tau=tau, storage=storage, schedule=schedule).bind()
-    N = g.n
-    u = np.zeros((3, N))
-    u[0] = 0.05
-    g.init_equilibrium(np.ones(N), u)
-    return g, fluid
-
-
-def taylor_green(lbm, workloads, n=256, collision=1, storage=0):
-    k = 2 * math.pi / n
-    rho, u = workloads.taylor_green_3d(n, 0.05)
-    tau = workloads.tau_for_reynolds(1600.0, 0.05, k)
-    g = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau, collision=collision, storage=storage).bind()
-    g.init_equilibrium(rho.reshape(-1), u.reshape(-1, 3).T.copy())
-    return g
-
-
-def multires_sphere(lbm, workloads, storage=0, schedule=1, scale=1):
-    """Flow past a sphere, 3 levels, coarsest 128x64x64 (finest 512x256x256),
-    sphere radius 16 finest cells at (128, 128, 128), finest level within 24
-    cells of the sphere, level 1 within a further 48; regularized inlet and
-    outlet on x, periodic y and z, tau_coarsest = 0.52.  scale=2 doubles
-    every length (the same shape at 8x the voxels)."""
-    n = (512 * scale, 256 * scale, 256 * scale)
-    lm, fluid = workloads.multires_sphere(*n, levels=3, center=(128.0 * scale,) * 3,
-                                          radius=16.0 * scale, bands=(24.0 * scale, 48.0 * scale))
-    faces = {lbm.XMIN: (lbm.BC_REG_VELOCITY, (0.05, 0.0, 0.0)),
-             lbm.XMAX: (lbm.BC_REG_PRESSURE, (1.0, 0.0, 0.0))}
-    g = lbm.Grid(*n, kind=lbm.MULTIRES, levels=3, level_map=lm, fluid=fluid, periodic=(False, True, True),
-                 faces=faces, tau=0.52, storage=storage, schedule=schedule).bind()
-    for l in range(3):
-        N = g.n_level(l)
-        u = np.zeros((3, N))
-        u[0] = 0.05
-        g.init_equilibrium(np.ones(N), u, level=l)
-    # updates per coarse step: every level-l voxel updates 2^(L-1-l) times
-    g.updates_per_step = sum(g.n_level(l) * 2 ** (2 - l) for l in range(3))
-    return g
+def closure_net(torch, lbm, workloads, cases):
+    """The learned closure for the MLP arms: the trained weights shipped with
+    the package when present, else He-uniform weights standardized on
+    samples of a regularized Taylor-Green run (same cost per update)."""
+    from paper_2503_07898_amd import train_closure
+    net = lbm.Mlp()
+    w = train_closure.load()
+    if w is not None:
+        net.set_params(w[0])
+        net.set_standardization(w[1])
+        return net, "trained"
+    net.set_params(lbm.flatten_params(workloads.mlp_he_uniform(7898)))
+    g = cases.taylor_green(n=64, re=400.0, collision=lbm.REGULARIZED)
+    g.step(50)
+    net.fit_standardization(g.sample(1, 200_000))
+    g.close()
+    return net, "untrained"
 
 
 def time_steps(torch, g, steps: int, warmup: int) -> float:
@@ -154,10 +120,18 @@ def measured_traffic(kernel: str):
 
 
 def cpu_baseline(workloads, budget_s: float = 15.0):
-    """The FP64 oracle on the same cavity (256^3, full box) for as many whole
-    steps as fit in about budget_s seconds (at least 1)."""
+    """The FP64 oracle on the same cavity (256^3, full box): as many whole
+    steps as fit in about budget_s seconds (at least 1) on every OpenMP
+    thread, plus one step on a single thread."""
+    import ctypes
     from oracle import oracle as orc
     orc.build()
+    L = orc.lib()
+    omp_max = L.omp_get_max_threads
+    omp_max.restype = ctypes.c_int
+    omp_set = L.omp_set_num_threads
+    omp_set.argtypes = [ctypes.c_int]
+    threads = int(omp_max())
     n = 256
     bc = [(orc.BB, (0, 0, 0))] * 5 + [(orc.MOVING, (0.1, 0.0, 0.0))]
     g = orc.Grid(n, n, n, periodic=(False,) * 3, bc=bc, tau=0.55)
@@ -171,15 +145,15 @@ def cpu_baseline(workloads, budget_s: float = 15.0):
         f = g.run(f, extra)
     dt = t1 + (time.perf_counter() - t0)
     steps = 1 + extra
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    try:
-        threads = min(threads, len(os.sched_getaffinity(0)))
-    except AttributeError:
-        pass
+    omp_set(1)
+    t0 = time.perf_counter()
+    g.run(f, 1)
+    dt1 = time.perf_counter() - t0
+    omp_set(threads)
     return {"value": round(n ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"FP64 oracle, dense lid-driven cavity 256^3 (full box), {steps} step(s), "
-                      f"{dt:.1f} s, OpenMP threads={threads}"}
+            "kind": "oracle", "value_1_thread": round(n ** 3 / dt1 / 1e6, 3),
+            "sample": f"FP64 oracle, dense lid-driven cavity 256^3 (full box), {steps} step(s) in "
+                      f"{dt:.1f} s on {threads} OpenMP threads; 1 step in {dt1:.1f} s on 1 thread"}
 
 
 def main(argv=None) -> int:
@@ -199,7 +173,7 @@ def main(argv=None) -> int:
         return 2
 
     import torch
-    from paper_2503_07898_amd import lbm, workloads
+    from paper_2503_07898_amd import cases, lbm, workloads
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
@@ -216,7 +190,7 @@ def main(argv=None) -> int:
 
     # ---------------- headline: cavity 256^3, FP32, disaggregated ----------
     log("cavity 256^3 FP32 disaggregated")
-    g = cavity(lbm)
+    g = cases.cavity()
     N = g.n
     dt, wall = time_steps(torch, g, args.steps, args.warmup)
     mlups = N * args.steps / dt / 1e6
@@ -227,7 +201,7 @@ def main(argv=None) -> int:
     upd_full = int(gf) * 64
     alg_bytes = upd_full * BYTES_PER_UPDATE[0]
     achieved = alg_bytes / t_full / 1e9
-    kname = "k_block_interior<StoreF32, 0, false>"
+    kname = "lbm::k19::k_block_interior<lbm::k19::StoreF32, 0, false, true>"
     traffic = measured_traffic(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -240,7 +214,7 @@ def main(argv=None) -> int:
 
     arms = {}
     if args.arms == "all":
-        def arm(name, make, steps, bytes_per_update):
+        def arm(name, make, steps, bytes_per_update, interior=False):
             log(name)
             gg = make()
             n_up = getattr(gg, "updates_per_step", None) or gg.n
@@ -249,25 +223,65 @@ def main(argv=None) -> int:
             arms[name] = {"MLUPS": round(m, 1),
                           "hbm_frac_alg": round(m * 1e6 * bytes_per_update / 1e9 / HBM_PEAK_GBS, 4),
                           "fluid_voxels": n_up, "launch_blocks": gg.launches()}
+            if interior:
+                # the interior (full-group) launch alone: HBM and matrix-core shares
+                _, _, _, nf, _ = gg.index_map(lbm.MAP_GROUPS)
+                t = time_launch(torch, lbm, gg, gg.launches().index(int(nf)), 20)
+                ups = int(nf) * 64
+                arms[name]["interior_launch"] = {
+                    "avg_launch_us": round(t * 1e6, 2), "updates": ups,
+                    "hbm_GBs": round(ups * bytes_per_update / t / 1e9, 1),
+                    "hbm_frac": round(ups * bytes_per_update / t / 1e9 / HBM_PEAK_GBS, 4),
+                    "mfma_TFLOPs_bf16": round(ups * MLP_MFMA_FLOPS / t / 1e12, 1),
+                    "mfma_frac": round(ups * MLP_MFMA_FLOPS / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
             gg.close()
             torch.cuda.empty_cache()
 
-        arm("cavity256_f32_plain_lexicographic", lambda: cavity(lbm, schedule=0), 100, 152)
-        arm("cavity256_f16_disagg", lambda: cavity(lbm, storage=1), 100, 76)
-        arm("cavity256_bf16_disagg", lambda: cavity(lbm, storage=2), 100, 76)
-        for st, bpu in ((0, 152), (1, 76)):
-            for sch, nm in ((0, "naive_single_kernel"), (1, "disagg_grouped")):
+        arm("cavity256_f32_plain_lexicographic", lambda: cases.cavity(schedule=lbm.PLAIN_SINGLE_KERNEL), 100, 152)
+        arm("cavity256_f16_disagg", lambda: cases.cavity(storage=lbm.F16_SHIFTED), 100, 76)
+        arm("cavity256_bf16_disagg", lambda: cases.cavity(storage=lbm.BF16_SHIFTED), 100, 76)
+        for st, bpu in ((lbm.F32, 152), (lbm.F16_SHIFTED, 76)):
+            for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "naive_single_kernel"), (lbm.DISAGG, "disagg_grouped"),
+                            (lbm.DISAGG_BITMASK, "disagg_bitmask")):
                 arm(f"tunnel512x256x256_{['f32', 'f16'][st]}_{nm}",
-                    lambda st=st, sch=sch: tunnel(lbm, workloads, storage=st, schedule=sch)[0], 50, bpu)
-        for st, bpu in ((0, 152), (1, 76)):
-            for sch, nm in ((0, "unfused_baseline"), (1, "disagg_fused")):
+                    lambda st=st, sch=sch: cases.tunnel(storage=st, schedule=sch), 50, bpu)
+        for st, bpu in ((lbm.F32, 152), (lbm.F16_SHIFTED, 76)):
+            for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"), (lbm.DISAGG, "disagg_fused")):
                 arm(f"multires_sphere_c128_{['f32', 'f16'][st]}_{nm}",
-                    lambda st=st, sch=sch: multires_sphere(lbm, workloads, storage=st, schedule=sch), 50, bpu)
-        for sch, nm in ((0, "unfused_baseline"), (1, "disagg_fused")):
+                    lambda st=st, sch=sch: cases.multires_sphere(storage=st, schedule=sch), 50, bpu)
+        for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"), (lbm.DISAGG, "disagg_fused")):
             arm(f"multires_sphere_c256_f32_{nm}",
-                lambda sch=sch: multires_sphere(lbm, workloads, schedule=sch, scale=2), 20, 152)
-        arm("taylor_green256_re1600_f32_regularized", lambda: taylor_green(lbm, workloads, collision=1), 100, 152)
-        arm("taylor_green256_re1600_f32_bgk", lambda: taylor_green(lbm, workloads, collision=0), 100, 152)
+                lambda sch=sch: cases.multires_sphere(schedule=sch, scale=2), 20, 152)
+        # D3Q27 (the lattice of the paper's block-sparse register study):
+        # 27 reads + 27 writes per update
+        for st, bpu in ((lbm.F32, 216), (lbm.F16_SHIFTED, 108)):
+            for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "naive_single_kernel"), (lbm.DISAGG, "disagg_grouped"),
+                            (lbm.DISAGG_BITMASK, "disagg_bitmask")):
+                arm(f"tunnel512x256x256_d3q27_{['f32', 'f16'][st]}_{nm}",
+                    lambda st=st, sch=sch: cases.tunnel(storage=st, schedule=sch, q=27), 50, bpu)
+        arm("cavity256_d3q27_f32_disagg", lambda: cases.cavity(q=27), 50, 216)
+        # the paper's own multires benchmark shape: lid-driven cavity, 512^3
+        # finest box, 77.6M / 4.09M / 0.37M voxels on levels 0 / 1 / 2
+        for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"), (lbm.DISAGG, "disagg_fused")):
+            arm(f"multires_cavity512_f32_{nm}", lambda sch=sch: cases.multires_cavity(schedule=sch), 10, 152)
+        arm("taylor_green256_re1600_f32_regularized",
+            lambda: cases.taylor_green(collision=lbm.REGULARIZED), 100, 152)
+        arm("taylor_green256_re1600_f32_bgk", lambda: cases.taylor_green(collision=lbm.BGK), 100, 152)
+        # the learned closure in place of the collision operator
+        net, which = closure_net(torch, lbm, workloads, cases)
+
+        def with_net(g):
+            g.set_collision(lbm.MLP, net)
+            return g
+
+        for name, make in (("taylor_green256_re1600_f32_mlp", lambda: cases.taylor_green()),
+                           ("cavity256_f32_mlp", lambda: cases.cavity()),
+                           ("cavity256_f16_mlp", lambda: cases.cavity(storage=lbm.F16_SHIFTED))):
+            net.fallbacks(reset=True)
+            arm(name, lambda make=make: with_net(make()), 50, 76 if "f16" in name else 152, interior=True)
+            arms[name]["closure"] = which
+            arms[name]["fallbacks"] = net.fallbacks()
+        net.close()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -6,6 +6,7 @@ Each builder creates, binds and initializes a grid with the seeded inputs of
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -13,30 +14,38 @@ import numpy as np
 from . import lbm, workloads
 
 
-def cavity(n=256, storage=lbm.F32, schedule=lbm.DISAGG, tau=0.55, uw=0.1, collision=lbm.BGK):
+def cavity(n=256, storage=lbm.F32, schedule=lbm.DISAGG, tau=0.55, uw=0.1, collision=lbm.BGK, q=19):
     """Dense lid-driven cavity n^3 at rest, bounce-back walls, lid z+ moving
     with (uw, 0, 0)."""
     faces = {f: (lbm.BC_BOUNCE_BACK, (0, 0, 0)) for f in range(6)}
     faces[lbm.ZMAX] = (lbm.BC_MOVING_WALL, (uw, 0.0, 0.0))
     g = lbm.Grid(n, n, n, kind=lbm.DENSE, periodic=(False,) * 3, faces=faces, tau=tau, storage=storage,
-                 schedule=schedule, collision=collision).bind()
+                 schedule=schedule, collision=collision, q=q).bind()
     N = g.n
     g.init_equilibrium(np.ones(N), np.zeros((3, N)))
     g.updates_per_step = N
     return g
 
 
-def tunnel(storage=lbm.F32, schedule=lbm.DISAGG, tau=0.6, n=(512, 256, 256), collision=lbm.BGK, seed=7898):
+@functools.lru_cache(maxsize=2)
+def _packing(n, seed):
+    fluid, _ = workloads.sphere_packing(*n, seed=seed)
+    fluid.setflags(write=False)
+    return fluid
+
+
+def tunnel(storage=lbm.F32, schedule=lbm.DISAGG, tau=0.6, n=(512, 256, 256), collision=lbm.BGK, seed=7898,
+           q=19):
     """Block-sparse wind tunnel through a seeded sphere packing (<= 30% of
     4^3 blocks active), velocity inlet 0.05 on x-, pressure outlet rho = 1 on
     x+, bounce-back walls on y and z."""
-    fluid, _ = workloads.sphere_packing(*n, seed=seed)
+    fluid = _packing(tuple(n), seed)
     faces = {lbm.XMIN: (lbm.BC_REG_VELOCITY, (0.05, 0.0, 0.0)),
              lbm.XMAX: (lbm.BC_REG_PRESSURE, (1.0, 0.0, 0.0))}
     for f in (lbm.YMIN, lbm.YMAX, lbm.ZMIN, lbm.ZMAX):
         faces[f] = (lbm.BC_BOUNCE_BACK, (0, 0, 0))
     g = lbm.Grid(*n, kind=lbm.BLOCK_SPARSE, periodic=(False,) * 3, fluid=fluid, faces=faces, tau=tau,
-                 storage=storage, schedule=schedule, collision=collision).bind()
+                 storage=storage, schedule=schedule, collision=collision, q=q).bind()
     N = g.n
     u = np.zeros((3, N))
     u[0] = 0.05

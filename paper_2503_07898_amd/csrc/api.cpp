@@ -63,6 +63,7 @@ struct LevelRT {
 
 struct lbm_mlp {
   size_t total = 0;
+  float judge = 0.01f;  // relative L2 tolerance of the closure against the regularized f1
   size_t off_params = 0, off_m = 0, off_v = 0, off_grads = 0, off_w = 0, off_bias = 0, off_stdz = 0,
          off_fb = 0, off_save = 0, off_dyt = 0, off_dz1 = 0, off_dz2 = 0, off_partial = 0, off_loss = 0;
   char *ws = nullptr;
@@ -138,6 +139,7 @@ StepArgs level_args(const lbm_grid *g, const LevelRT &r) {
     a.mlp_bias = g->mlp->B.bias;
     a.mlp_stdz = g->mlp->B.stdz;
     a.mlp_fallbacks = g->mlp->B.fallbacks;
+    a.mlp_judge = g->mlp->judge;
   }
   return a;
 }
@@ -799,6 +801,12 @@ lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f, const int64_t *idx, in
   hipError_t e = mlp_gradients(m->B, f, idx, n, loss, s);
   if (!e) e = mlp_adam(m->B, lr, t, s);
   if (e) return hip_fail(e, "mlp_train_step");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_set_judge(lbm_mlp *m, double rel_tol) {
+  if (!m || !(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(LBM_ERR_INVALID_ARG, "bad judge tolerance");
+  m->judge = (float)rel_tol;
   return LBM_OK;
 }
 

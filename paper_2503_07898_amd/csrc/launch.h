@@ -33,6 +33,7 @@ struct StepArgs {
   const float *mlp_bias;          // b1 | b2 | b3
   const float *mlp_stdz;          // in_mean | in_inv_std | out_std | out_mean (32 each)
   unsigned int *mlp_fallbacks;    // voxels that fell back to the regularized operator
+  float mlp_judge;                // relative L2 tolerance against the regularized f1 (0 = off)
   // bitmask-based grouping
   const uint32_t *bbits;          // [(nblocks+31)/32] bit set = boundary block
   const int32_t *vid;             // [S] boundary record of the slot, -1 = none

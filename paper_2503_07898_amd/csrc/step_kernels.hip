@@ -126,8 +126,10 @@ __global__ __launch_bounds__(256) void k_block_interior_bits(StepArgs a, int32_t
 // Same gather as k_block_interior; the collision evaluates the closure
 // network for the wave's 64 voxels on the matrix cores, projects its output
 // to zero mass and momentum, and falls back per voxel to the regularized
-// operator when a standardized input leaves [-8, 8] or a population turns
-// negative.  The packed weights are staged in LDS once per workgroup.
+// operator when a standardized input leaves [-8, 8], a population turns
+// negative, or the closure's non-equilibrium part strays more than the
+// judge tolerance from the regularized operator's.  The packed weights are
+// staged in LDS once per workgroup.
 template <class ST, bool MASKED>
 __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t g0, int32_t n) {
   using T = typename ST::T;
@@ -186,6 +188,22 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
 #pragma unroll
   for (int i = 0; i < Q; ++i) y[i] = fmaf(y[i], sd[64 + i], sd[96 + i]);
   project_out(y);
+  // the regularized operator judges the closure: its non-equilibrium part
+  // f1/rho must lie within judge (relative L2) of the closure's
+  bool off = false;
+  if (a.mlp_judge > 0.0f) {
+    float f1[Q];
+    f1_projection(h, m, f1);
+    float d2 = 0.0f, t2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float t = f1[i] * ir;
+      const float d = y[i] - t;
+      d2 = fmaf(d, d, d2);
+      t2 = fmaf(t, t, t2);
+    }
+    off = d2 > a.mlp_judge * a.mlp_judge * t2;
+  }
   float hs[Q];
   const float r = (1.0f - a.omega) * m.rho;
   bool negative = false;
@@ -194,7 +212,7 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
     hs[i] = fmaf(r, y[i], heq[i]);
     negative = negative || (weight_f(i) + hs[i] < 0.0f);
   }
-  const bool fb = fluid && (out_of_range || negative);
+  const bool fb = fluid && (out_of_range || negative || off);
   if (fb) collide_regularized_m(h, m, a.omega);
   else
 #pragma unroll

@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
             "lbm_mlp_forward": ([vp, vp, i64, vp, vp], i32),
             "lbm_mlp_gradients": ([vp, vp, vp, i64, vp, vp, vp], i32),
             "lbm_mlp_train_step": ([vp, vp, vp, i64, ctypes.c_float, i32, vp, vp], i32),
+            "lbm_mlp_set_judge": ([vp, ctypes.c_double], i32),
             "lbm_mlp_fallbacks": ([vp, ctypes.POINTER(ctypes.c_uint64), i32, vp], i32),
             "lbm_mlp_destroy": ([vp], i32),
             "lbm_set_collision": ([vp, i32, vp], i32),
@@ -246,6 +247,10 @@ def lbm_mlp_train_step(m, f_ptr: int, idx_ptr, n: int, lr: float, t: int, loss_p
                        stream=None) -> None:
     check(lib().lbm_mlp_train_step(m, f_ptr, idx_ptr, int(n), float(lr), int(t), loss_ptr,
                                    _stream_ptr(stream)))
+
+
+def lbm_mlp_set_judge(m, rel_tol: float) -> None:
+    check(lib().lbm_mlp_set_judge(m, ctypes.c_double(rel_tol)))
 
 
 def lbm_mlp_fallbacks(m, reset: bool = False, stream=None) -> int:
@@ -447,6 +452,9 @@ class Mlp:
         n = f.shape[0] if idx is None else idx.shape[0]
         lbm_mlp_train_step(self.h, f.data_ptr(), None if idx is None else idx.data_ptr(), n, lr, t,
                            None if loss is None else loss.data_ptr())
+
+    def set_judge(self, rel_tol: float) -> None:
+        lbm_mlp_set_judge(self.h, rel_tol)
 
     def fallbacks(self, reset: bool = False) -> int:
         return lbm_mlp_fallbacks(self.h, reset)

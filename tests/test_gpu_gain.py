@@ -1,0 +1,159 @@
+"""What the trained closure gains over the operators without it (MI355X).
+
+Taylor-Green vortex at tau ~ 0.5038, FP32 arms on the GPU: BGK, the
+regularized operator, the learned closure with the shipped weights (trained
+on regularized runs of the cavity, the wind tunnel and the multires sphere,
+not on this flow) with the run-time judge at 1% and without it, and the same
+network untrained (He-uniform weights, same standardization, judge 1%).
+Each arm is compared with the FP64 regularized oracle at one and two
+convective times t_c = 1/(k u0): relative L2 of u, the kinetic energy curve
+at every t_c/8, the first checkpoint with a non-finite energy, and for the
+closure arms the fraction of updates that fell back to the regularized
+operator (the share the network did not supply).
+
+Default size 64^3 at Re = 400, which has the same tau as 256^3 at Re = 1600.
+The full-size case (256^3, Re = 1600, 815 and 1630 steps) runs when
+LBM_FULL_GAIN=1; its FP64 oracle then takes several minutes.
+
+Asserted: the regularized arm tracks the FP64 oracle; the judged closure
+conserves mass and stays within 1e-2 of it; the trained network supplies
+more of the updates than the untrained one.  Accuracy relative to BGK and
+the unjudged closure are reported, not asserted (a null result is a
+result).
+"""
+import json
+import math
+import os
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+from paper_2503_07898_amd import lbm, train_closure, workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U0 = 0.05
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lbm.lib()
+
+
+def kinetic_energy(rho, u):
+    """0.5 sum rho |u|^2 (rho [N], u [N][3])."""
+    return 0.5 * float(np.sum(rho * np.sum(u * u, axis=1)))
+
+
+def oracle_curve(orc, n, tau, rho0, u0, checkpoints, keep, out):
+    og = orc.Grid(n, n, n, tau=tau, collision=orc.REGULARIZED)
+    f = og.init_equilibrium(rho0, u0)
+    done = 0
+    for s in checkpoints:
+        f = og.run(f, s - done)
+        done = s
+        r, v = og.macroscopic(f)
+        r = r.reshape(-1)
+        v = v.reshape(-1, 3)
+        out[s] = (kinetic_energy(r, v), v.copy() if s in keep else None)
+
+
+def gpu_arm(n, tau, rho0, u0, checkpoints, keep, collision, net=None, judge=0.01):
+    g = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau,
+                 collision=lbm.BGK if collision == lbm.MLP else collision).bind()
+    if collision == lbm.MLP:
+        net.set_judge(judge)
+        g.set_collision(lbm.MLP, net)
+        net.fallbacks(reset=True)
+    g.init_equilibrium(rho0.reshape(-1), u0.reshape(-1, 3).T.copy())
+    m0 = g.reduce().cpu().numpy()[0]
+    res, first_bad, done = {}, None, 0
+    for s in checkpoints:
+        g.step(s - done)
+        done = s
+        r, v = g.macroscopic()
+        r = r.cpu().numpy()
+        v = v.cpu().numpy().T
+        if not (np.all(np.isfinite(v)) and np.all(np.isfinite(r))):
+            first_bad = s
+            break
+        res[s] = (kinetic_energy(r, v), v if s in keep else None)
+    m1 = g.reduce().cpu().numpy()[0]
+    fb = net.fallbacks() / (n ** 3 * done) if net is not None else 0.0
+    g.close()
+    return res, first_bad, abs(m1 - m0) / m0 if first_bad is None else float("nan"), fb
+
+
+def run_gain(orc, n, re):
+    w = train_closure.load()
+    if w is None:
+        pytest.skip("no trained closure weights shipped (run paper_2503_07898_amd.train_closure)")
+    k = 2 * math.pi / n
+    tau = workloads.tau_for_reynolds(re, U0, k)
+    tc = 1.0 / (k * U0)
+    checkpoints = sorted({int(round(tc * j / 8)) for j in range(1, 17)})
+    s1, s2 = int(round(tc)), int(round(2 * tc))
+    assert s1 in checkpoints and s2 in checkpoints
+    rho0, u0 = workloads.taylor_green_3d(n, U0)
+    _say(f"  Taylor-Green {n}^3 Re={re} tau={tau:.6f} t_c={tc:.1f} steps; checkpoints {checkpoints}")
+
+    ref = {}
+    th = threading.Thread(target=oracle_curve, args=(orc, n, tau, rho0, u0, checkpoints, (s1, s2), ref))
+    th.start()
+
+    trained = lbm.Mlp()
+    trained.set_params(w[0])
+    trained.set_standardization(w[1])
+    untrained = lbm.Mlp()
+    untrained.set_params(lbm.flatten_params(workloads.mlp_he_uniform(7898)))
+    untrained.set_standardization(w[1])
+    arms = {}
+    for name, coll, net, judge in (("bgk", lbm.BGK, None, 0.0), ("regularized", lbm.REGULARIZED, None, 0.0),
+                                   ("mlp_trained", lbm.MLP, trained, 0.01),
+                                   ("mlp_untrained", lbm.MLP, untrained, 0.01),
+                                   ("mlp_trained_no_judge", lbm.MLP, trained, 0.0)):
+        arms[name] = gpu_arm(n, tau, rho0, u0, checkpoints, (s1, s2), coll, net, judge)
+    trained.close()
+    untrained.close()
+    th.join()
+
+    table = {}
+    for name, (res, bad, drift, fb) in arms.items():
+        row = {"first_nonfinite_checkpoint": bad, "mass_drift": drift, "fallback_fraction": fb}
+        for s, lab in ((s1, "t_c"), (s2, "2t_c")):
+            if s in res:
+                ke_ref, u_ref = ref[s]
+                row[f"rel_l2_u_{lab}"] = float(np.linalg.norm(res[s][1] - u_ref) / np.linalg.norm(u_ref))
+                row[f"ke_rel_{lab}"] = res[s][0] / ke_ref - 1.0
+            else:
+                row[f"rel_l2_u_{lab}"] = float("inf")
+        row["ke_curve_rel"] = [round(res[s][0] / ref[s][0] - 1.0, 6) if s in res else None for s in checkpoints]
+        table[name] = row
+        _say(f"  {name:14s} u@t_c {row['rel_l2_u_t_c']:.3e}  u@2t_c {row['rel_l2_u_2t_c']:.3e}  "
+             f"first non-finite {bad}  mass drift {drift:.1e}  fallback fraction {fb:.3f}")
+    _say("  GAIN " + json.dumps({"n": n, "re": re, "tau": tau, "checkpoints": checkpoints, "arms": table}))
+    assert table["regularized"]["rel_l2_u_2t_c"] < 1e-4
+    assert table["mlp_trained"]["first_nonfinite_checkpoint"] is None
+    assert table["mlp_trained"]["mass_drift"] < 1e-6
+    assert table["mlp_trained"]["rel_l2_u_2t_c"] < 1e-2
+    assert table["mlp_trained"]["fallback_fraction"] < table["mlp_untrained"]["fallback_fraction"]
+    return table
+
+
+def test_gain_taylor_green_64(orc):
+    run_gain(orc, 64, 400.0)
+
+
+@pytest.mark.skipif(os.environ.get("LBM_FULL_GAIN") != "1", reason="full-size gain study: set LBM_FULL_GAIN=1")
+def test_gain_taylor_green_256(orc):
+    run_gain(orc, 256, 1600.0)

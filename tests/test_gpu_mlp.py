@@ -88,6 +88,49 @@ def test_forward_and_gradients_match_oracle(orc, mlpo):
     m.close()
 
 
+def test_closure_step_matches_oracle(orc, mlpo):
+    """One solver step with the closure against the oracle's closure
+    (stream, then collide with the same bf16-rounded weights), on a
+    non-equilibrium state of a regularized Taylor-Green run."""
+    n, tau = 16, 0.6
+    rho, u = workloads.taylor_green_3d(n, 0.05)
+    src = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau, collision=lbm.REGULARIZED).bind()
+    src.init_equilibrium(rho.reshape(-1), u.reshape(-1, 3).T.copy())
+    src.step(5)
+    f0 = src.populations().cpu().numpy()  # post-collision state [19][N]
+    data = src.sample(1, 20_000)
+    src.close()
+    m = lbm.Mlp()
+    m.set_params(lbm.flatten_params(workloads.mlp_he_uniform(9)))
+    m.fit_standardization(data)
+    for storage, judge in ((lbm.F32, 0.0), (lbm.F16_SHIFTED, 0.0), (lbm.F32, 0.01)):
+        m.set_judge(judge)
+        g = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau, storage=storage).bind()
+        g.set_collision(lbm.MLP, m)
+        g.write_populations(f0)
+        start = g.populations().cpu().numpy()  # the stored (rounded) state
+        m.fallbacks(reset=True)
+        g.step(1)
+        f1 = g.populations().cpu().numpy().T
+        fb = m.fallbacks()
+        g.close()
+        c, _, _ = orc.lattice()
+        pre = np.empty_like(start)
+        for i in range(19):
+            pre[i] = np.roll(start[i].reshape(n, n, n), shift=(c[i][2], c[i][1], c[i][0]),
+                             axis=(0, 1, 2)).reshape(-1)
+        p = oracle_params(mlpo, lbm.unflatten_params(m.params()), m.standardization())
+        ref, fell = mlpo.collide(p, pre.T, tau, judge=judge)
+        feq = np.array([orc.equilibrium(*orc.moments(ref[k])) for k in range(ref.shape[0])])
+        e = rel(f1 - feq, ref - feq)
+        _say(f"  storage {storage} judge {judge}: rel L2 of f* - f^eq vs oracle closure {e:.2e}, "
+             f"fallbacks gpu {fb} oracle {int(fell.sum())}")
+        assert e < 1e-2
+        # decisions taken in different precisions may differ at the threshold
+        assert abs(fb - int(fell.sum())) <= max(2, fell.size // 200)
+    m.close()
+
+
 def regularized_tg_samples(n_samples, seed, n=32, steps=40):
     """Populations from a regularized-operator run of a 3D Taylor-Green vortex."""
     rho, u = workloads.taylor_green_3d(n, 0.05)
@@ -128,6 +171,12 @@ def test_training_lowers_loss():
 
 
 def test_closure_in_solver(orc):
+    """Taylor-Green at tau 0.5038 (Re 200 on 32^3), closure trained briefly on
+    the solver's own regularized populations, run-time judge at its default
+    (1%): within 1e-2 of the FP64 regularized operator, mass conserved, and
+    the trained network keeps more of its own updates than the untrained one.
+    Without the judge the errors are reported (near tau = 1/2 an overshoot of
+    the regularized stress above 1.5% is unstable)."""
     n = 32
     data = regularized_tg_samples(200_000, 3)
     m = lbm.Mlp()
@@ -144,8 +193,11 @@ def test_closure_in_solver(orc):
     fo = og.run(og.init_equilibrium(rho, u), steps)
     _, uo = og.macroscopic(fo)
     uo = uo.reshape(-1, 3)
-    errs = {}
-    for name, net, coll in (("mlp", m, lbm.MLP), ("untrained", untrained, lbm.MLP), ("bgk", None, lbm.BGK)):
+    errs, fbs = {}, {}
+    for name, net, coll, judge in (("mlp", m, lbm.MLP, 0.01), ("untrained", untrained, lbm.MLP, 0.01),
+                                   ("mlp_nojudge", m, lbm.MLP, 0.0), ("bgk", None, lbm.BGK, 0.0)):
+        if net is not None:
+            net.set_judge(judge)
         g = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau).bind()
         g.set_collision(coll, net)
         g.init_equilibrium(rho.reshape(-1), u.reshape(-1, 3).T.copy())
@@ -158,12 +210,13 @@ def test_closure_in_solver(orc):
         v = v.cpu().numpy().T
         errs[name] = rel(v, uo) if np.all(np.isfinite(v)) else float("inf")
         fb = net.fallbacks() if net is not None else 0
+        fbs[name] = fb / (n ** 3 * steps)
         _say(f"  {name}: rel L2 u vs FP64 regularized = {errs[name]:.3e}, mass drift "
-             f"{abs(m1 - m0) / m0:.1e}, fallbacks {fb}")
+             f"{abs(m1 - m0) / m0:.1e}, fallback fraction {fbs[name]:.3f}")
         if name == "mlp":
             assert abs(m1 - m0) / m0 < 1e-6
         g.close()
     assert errs["mlp"] < 1e-2
-    assert errs["mlp"] < errs["untrained"]
+    assert fbs["mlp"] <= fbs["untrained"]
     m.close()
     untrained.close()
