@@ -10,11 +10,15 @@ timed region starts.
 
 Printed: one JSON line with MLUPS (million fluid-voxel updates per second),
 the roofline of the dominant kernel (the interior-group kernel; 152 bytes
-per FP32 update = 19 population reads + 19 writes, against 8 TB/s HBM), the
-other arms (lexicographic single kernel, FP16/BF16-shifted storage, the
-block-sparse wind tunnel with naive vs grouped kernels, the regularized
-operator) and the FP64 CPU oracle timed on the host on a bounded sample of
-the same workload.
+per FP32 update = 19 population reads + 19 writes, against 8 TB/s HBM, with
+the measured HBM traffic when a counter summary of the same kernel source is
+committed), the FP64 CPU oracle timed on the host on a bounded sample of the
+same workload, and the other arms: lexicographic single kernel, FP16/BF16-
+shifted storage, the block-sparse wind tunnel with the naive kernel against
+memory-based and bitmask-based grouping (D3Q19 and D3Q27), the multires
+sphere and the multires lid-driven cavity (unfused baseline against fused),
+the regularized operator and the learned closure (with the share of HBM and
+matrix-core peak of its interior launch).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--arms all|none]
 """
@@ -208,6 +212,18 @@ def main(argv=None) -> int:
                 "kernel": kname, "launch_blocks": int(gf), "updates_per_launch": upd_full,
                 "bytes_per_update": BYTES_PER_UPDATE[0], "avg_launch_us": round(t_full * 1e6, 2)}
     step_frac = mlups * 1e6 * BYTES_PER_UPDATE[0] / 1e9 / HBM_PEAK_GBS
+    # off the timed loop: FP64 reductions and the macroscopic read-out
+    aux = {}
+    for name, fn in (("reduce_fp64_ms", g.reduce), ("read_macroscopic_fp32_ms", lambda: g.macroscopic(f64=False))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        aux[name] = round(e0.elapsed_time(e1) / 10, 3)
     g.close()
     del g
     torch.cuda.empty_cache()
@@ -296,7 +312,7 @@ def main(argv=None) -> int:
         "config": {"workload": "dense D3Q19 lid-driven cavity 256^3, FP32 shifted storage, "
                                "bounce-back walls, lid u=0.1, tau=0.55, disaggregated shell/interior kernels",
                    "fluid_voxels": N, "groups": {"shell": int(gb), "interior": int(gf)},
-                   "step_hbm_frac_alg": round(step_frac, 4), "wall_s": round(wall, 3)},
+                   "step_hbm_frac_alg": round(step_frac, 4), "wall_s": round(wall, 3), **aux},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "arms": arms,
