@@ -270,8 +270,10 @@ lbm_status lbm_mlp_gradients(lbm_mlp *m, const float *f_dev, const int64_t *idx_
 lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f_dev, const int64_t *idx_dev, int64_t n,
                               float lr, int32_t t, double *loss_dev, void *stream);
 /* Tolerance of the run-time judge (default 0.01): a voxel keeps the
- * closure's update only if |P(y) - f1/rho|_2 <= rel_tol |f1/rho|_2, with f1
- * the regularized operator's non-equilibrium part; 0 switches the judge off
+ * closure's update only if |P(y) - f1/rho|_2^2 <= rel_tol^2 (|f1/rho|_2^2 +
+ * |out_std|_2^2), with f1 the regularized operator's non-equilibrium part
+ * and out_std the output scale of the standardization (the floor lets voxels
+ * near equilibrium keep small absolute deviations); 0 switches the judge off
  * (the range and positivity tests remain).  Near tau = 1/2 an overshoot of
  * the regularized stress by more than 1/(1 - 1/tau) - 1 (1.5% at
  * tau = 0.5038) is unstable, which the default keeps out.  Takes effect at

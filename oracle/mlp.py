@@ -22,8 +22,10 @@ tau = 1/2 is relaxed with a factor close to -1 and grew in closed loop.)  A voxe
 falls back to the regularized operator if any standardized input exceeds 8
 in magnitude, if any output population is negative, or -- the regularized
 operator acting as judge of the closure's error -- if
-|P(y) - f1/rho|_2 > judge |f1/rho|_2 (judge = 0.01 by default; 0 disables
-the test).  Near tau = 1/2 the non-equilibrium part is relaxed by a factor
+|P(y) - f1/rho|_2^2 > judge^2 (|f1/rho|_2^2 + |out_std|_2^2) (judge = 0.01
+by default; 0 disables the test; the floor, the typical training-target
+size, lets voxels near equilibrium, whose f1 is almost zero, keep the
+network's update when its deviation is small in absolute terms).  Near tau = 1/2 the non-equilibrium part is relaxed by a factor
 close to -1, and a closure that overshoots the regularized stress by more
 than about 1/(1 - 1/tau) - 1 (1.5% at tau = 0.5038) makes that factor
 exceed 1 in magnitude; the judge keeps every accepted update inside it.  Training minimizes the
@@ -45,6 +47,7 @@ HIDDEN = 64
 Q = 19
 FALLBACK_LIMIT = 8.0
 JUDGE = 0.01
+JUDGE_FLOOR = 1.0
 
 
 def gelu(x):
@@ -211,7 +214,8 @@ def collide(p: Params, f, tau, y_override=None, judge: float = JUDGE):
         rho, u = _orc.moments(f[k])
         feq = _orc.equilibrium(rho, u)
         fs = feq + (1.0 - 1.0 / tau) * rho * py[k]
-        off = judge > 0 and np.sum((py[k] - t[k]) ** 2) > judge * judge * np.sum(t[k] ** 2)
+        floor2 = (JUDGE_FLOOR ** 2) * np.sum(p.out_std ** 2)
+        off = judge > 0 and np.sum((py[k] - t[k]) ** 2) > judge * judge * (np.sum(t[k] ** 2) + floor2)
         if np.any(np.abs(x[k]) > FALLBACK_LIMIT) or np.any(fs < 0) or off:
             fs = _orc.collide_regularized(f[k], tau)
             fell[k] = True

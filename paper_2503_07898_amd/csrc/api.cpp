@@ -260,6 +260,7 @@ SlotArgs slot_args(const lbm_grid *g, const LevelRT &r) {
   A.canon = r.L ? (const int32_t *)(g->ws + r.off_canon) : nullptr;
   A.n = r.n_fluid;
   A.storage = g->desc.storage;
+  A.blocked = r.L ? 1 : 0;
   return A;
 }
 

@@ -18,8 +18,8 @@ inline namespace LBM_LATTICE_NS {
 
 struct StoreF32 {
   using T = float;
-  static __device__ __forceinline__ float load(const T *p, uint32_t i) { return p[i]; }
-  static __device__ __forceinline__ void store(T *p, uint32_t i, float v) {
+  static __device__ __forceinline__ float load(const T *p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ void store(T *p, size_t i, float v) {
     __builtin_nontemporal_store(v, p + i);
   }
   static __device__ __forceinline__ float to_float(T v) { return v; }
@@ -39,10 +39,10 @@ __device__ __forceinline__ uint16_t f16_rne(float v) {
 
 struct StoreF16 {
   using T = uint16_t;
-  static __device__ __forceinline__ float load(const T *p, uint32_t i) {
+  static __device__ __forceinline__ float load(const T *p, size_t i) {
     return (float)__builtin_bit_cast(_Float16, p[i]);
   }
-  static __device__ __forceinline__ void store(T *p, uint32_t i, float v) {
+  static __device__ __forceinline__ void store(T *p, size_t i, float v) {
     __builtin_nontemporal_store(f16_rne(v), p + i);
   }
   static __device__ __forceinline__ T from_double(double d) {
@@ -62,10 +62,10 @@ __device__ __forceinline__ uint16_t bf16_rne(float v) {
 
 struct StoreBF16 {
   using T = uint16_t;
-  static __device__ __forceinline__ float load(const T *p, uint32_t i) {
+  static __device__ __forceinline__ float load(const T *p, size_t i) {
     return __uint_as_float((uint32_t)p[i] << 16);
   }
-  static __device__ __forceinline__ void store(T *p, uint32_t i, float v) {
+  static __device__ __forceinline__ void store(T *p, size_t i, float v) {
     __builtin_nontemporal_store(bf16_rne(v), p + i);
   }
   // round a double to 8 significant bits (nearest-even) without passing
@@ -81,6 +81,16 @@ struct StoreBF16 {
     return (double)__uint_as_float((uint32_t)v << 16);
   }
 };
+
+// ------------------------------------------------------ population layout --
+// Block layouts interleave the populations per block: the 64 slots of block
+// b in direction i are the 64 consecutive values starting at (b Q + i) 64, so
+// a block's Q rows form one contiguous span of Q x 64 values and every row
+// is still one coalesced wave access.  (The dense lexicographic arm keeps Q
+// separate planes of nx ny nz values.)
+__device__ __forceinline__ size_t pidx(int i, uint32_t slot) {
+  return ((size_t)(slot >> 6) * Q + (size_t)i) * 64 + (slot & 63u);
+}
 
 // ------------------------------------------------------- compile-time loop --
 template <int I, int N, class F>

@@ -56,7 +56,7 @@ enum KernelKind : int32_t {
 // own level one step back, finer level now, finer one step back, coarser now.
 struct MrArgs {
   const void *src[5];
-  uint32_t stride[5];
+  uint32_t stride[5];      // slots per buffer (informational)
   const uint32_t *jtab;   // [njump][2][19][64]
   const uint32_t *jlist;  // [nlist][8]
   int32_t phase;          // 0 or 1
@@ -109,6 +109,7 @@ struct SlotArgs {
   const int32_t *canon;      // [nslots] or NULL
   int64_t n;                 // canonical length
   int32_t storage;
+  int32_t blocked;           // 1: block-interleaved populations, 0: planes of S
 };
 
 // Launchers built once per lattice (step_kernels.hip and util_kernels.hip

@@ -71,7 +71,9 @@ struct MlpView {
 __device__ __forceinline__ float gelu_f(float x) {
   const float k2 = 2.0f * 0.7978845608028654f;
   const float z = k2 * fmaf(0.044715f * x, x * x, x);
-  return x / (1.0f + __expf(-z));
+  // x * sigmoid(2z) with the hardware reciprocal (about 1 ulp; the result
+  // is rounded to bf16 for the next layer) instead of an IEEE division
+  return x * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
 
 // derivative of gelu_f

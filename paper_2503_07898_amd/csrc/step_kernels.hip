@@ -68,7 +68,6 @@ __device__ __forceinline__ void interior_block(const StepArgs &a, int b) {
   const int lane = threadIdx.x & 63;
   const T *__restrict__ src = (const T *)a.src;
   T *__restrict__ dst = (T *)a.dst;
-  const uint32_t S = a.S;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
 
   int32_t nbv[kNbr];
@@ -81,7 +80,7 @@ __device__ __forceinline__ void interior_block(const StepArgs &a, int b) {
   }
 
   float h[Q];
-  h[0] = ST::load(src, own_slot);
+  h[0] = ST::load(src, pidx(0, own_slot));
   static_for<1, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     uint32_t slot = pull_slot<i>(lane, b, nbv);
@@ -92,13 +91,13 @@ __device__ __forceinline__ void interior_block(const StepArgs &a, int b) {
         plane = kOpp[i];
       }
     }
-    h[i] = ST::load(src + (size_t)plane * S, slot);
+    h[i] = ST::load(src, pidx(plane, slot));
   });
 
   if constexpr (FUSED) collide<COLL>(h, a.omega);
 
 #pragma unroll
-  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+  for (int i = 0; i < Q; ++i) ST::store(dst, pidx(i, own_slot), h[i]);
 }
 
 template <class ST, int COLL, bool MASKED, bool FUSED>
@@ -143,7 +142,6 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
   const int lane = threadIdx.x & 63;
   const T *__restrict__ src = (const T *)a.src;
   T *__restrict__ dst = (T *)a.dst;
-  const uint32_t S = a.S;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
   int32_t nbv[kNbr];
 #pragma unroll
@@ -154,7 +152,7 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
     for (int d = 0; d < kNbr; ++d) bm[d] = a.bbm[(size_t)b * kNbr + d];
   }
   float h[Q];
-  h[0] = ST::load(src, own_slot);
+  h[0] = ST::load(src, pidx(0, own_slot));
   static_for<1, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     uint32_t slot = pull_slot<i>(lane, b, nbv);
@@ -165,7 +163,7 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
         plane = kOpp[i];
       }
     }
-    h[i] = ST::load(src + (size_t)plane * S, slot);
+    h[i] = ST::load(src, pidx(plane, slot));
   });
   const bool fluid = MASKED ? ((a.fmask[b] >> lane) & 1ull) != 0 : true;
 
@@ -189,20 +187,22 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
   for (int i = 0; i < Q; ++i) y[i] = fmaf(y[i], sd[64 + i], sd[96 + i]);
   project_out(y);
   // the regularized operator judges the closure: its non-equilibrium part
-  // f1/rho must lie within judge (relative L2) of the closure's
+  // f1/rho must lie within judge (relative L2) of the closure's, with the
+  // typical target size as floor for voxels near equilibrium
   bool off = false;
   if (a.mlp_judge > 0.0f) {
     float f1[Q];
     f1_projection(h, m, f1);
-    float d2 = 0.0f, t2 = 0.0f;
+    float d2 = 0.0f, t2 = 0.0f, s2 = 0.0f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const float t = f1[i] * ir;
       const float d = y[i] - t;
       d2 = fmaf(d, d, d2);
       t2 = fmaf(t, t, t2);
+      s2 = fmaf(sd[64 + i], sd[64 + i], s2);
     }
-    off = d2 > a.mlp_judge * a.mlp_judge * t2;
+    off = d2 > a.mlp_judge * a.mlp_judge * (t2 + s2);
   }
   float hs[Q];
   const float r = (1.0f - a.omega) * m.rho;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
   const uint64_t bal = __ballot(fb);
   if (lane == 0 && bal) atomicAdd(a.mlp_fallbacks, (unsigned int)__popcll(bal));
 #pragma unroll
-  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+  for (int i = 0; i < Q; ++i) ST::store(dst, pidx(i, own_slot), h[i]);
 }
 
 #endif  // LBM_Q27
@@ -234,7 +234,6 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, int b) {
   const int lane = threadIdx.x & 63;
   const T *__restrict__ src = (const T *)a.src;
   T *__restrict__ dst = (T *)a.dst;
-  const uint32_t S = a.S;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
 
   int32_t nbv[kNbr];
@@ -262,7 +261,7 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, int b) {
   float h[Q];
   uint32_t unknown = 0;
   int rface = 0;
-  h[0] = ST::load(src, own_slot);
+  h[0] = ST::load(src, pidx(0, own_slot));
   static_for<1, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     const LinkClass lc = classify_link<i, REC>(a.fp, gx, gy, gz, a.nx, a.ny, a.nz, rv);
@@ -272,7 +271,7 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, int b) {
       slot = own_slot;
       plane = kOpp[i];
     }
-    float v = ST::load(src + (size_t)plane * S, slot);
+    float v = ST::load(src, pidx(plane, slot));
     if (lc.kind == kLinkMoving) v = v + lc.extra;
     if (lc.kind == kLinkUnknown) {
       unknown |= 1u << i;
@@ -287,7 +286,7 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, int b) {
   }
 
 #pragma unroll
-  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * S, own_slot, h[i]);
+  for (int i = 0; i < Q; ++i) ST::store(dst, pidx(i, own_slot), h[i]);
 }
 
 template <class ST, int COLL, bool FUSED>
@@ -320,11 +319,10 @@ __global__ __launch_bounds__(256) void k_block_collide(StepArgs a, int32_t g0, i
   if (b >= g0 + n) return;
   const int lane = threadIdx.x & 63;
   T *__restrict__ buf = (T *)a.dst;
-  const uint32_t S = a.S;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
   float h[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) h[i] = ST::load(buf + (size_t)i * S, own_slot);
+  for (int i = 0; i < Q; ++i) h[i] = ST::load(buf, pidx(i, own_slot));
   if constexpr (HEAVY) {
     const int packed = a.coords[b];
     const int gx = (packed & 1023) * 4 + (lane & 3);
@@ -346,7 +344,7 @@ __global__ __launch_bounds__(256) void k_block_collide(StepArgs a, int32_t g0, i
     collide<COLL>(h, a.omega);
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) ST::store(buf + (size_t)i * S, own_slot, h[i]);
+  for (int i = 0; i < Q; ++i) ST::store(buf, pidx(i, own_slot), h[i]);
 }
 
 #ifndef LBM_Q27  // D3Q19 only
@@ -363,13 +361,9 @@ __device__ __forceinline__ float mr_fetch(const MrArgs &m, uint32_t e, int plane
   const uint32_t slot = e & ((1u << 28) - 1u);
   const int pl = (e >> 28) & 1u ? opp_plane : plane;
   const T *base = (const T *)m.src[0];
-  uint32_t stride = m.stride[0];
 #pragma unroll
-  for (int t = 1; t < 5; ++t) {
-    base = tag == (uint32_t)t ? (const T *)m.src[t] : base;
-    stride = tag == (uint32_t)t ? m.stride[t] : stride;
-  }
-  return ST::load(base + (size_t)pl * stride, slot);
+  for (int t = 1; t < 5; ++t) base = tag == (uint32_t)t ? (const T *)m.src[t] : base;
+  return ST::load(base, pidx(pl, slot));
 }
 
 template <class ST, int COLL, bool FUSED>
@@ -398,7 +392,7 @@ __global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g
   });
   if constexpr (FUSED) collide<COLL>(h, a.omega);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) ST::store(dst + (size_t)i * a.S, own_slot, h[i]);
+  for (int i = 0; i < Q; ++i) ST::store(dst, pidx(i, own_slot), h[i]);
 }
 
 #endif  // LBM_Q27
@@ -484,7 +478,7 @@ __global__ void k_sample_pre(StepArgs a, int32_t b0, int32_t nb, uint64_t seed, 
   int32_t nbv[kNbr];
   for (int d = 0; d < kNbr; ++d) nbv[d] = a.nbr[(size_t)b * kNbr + d];
   const uint32_t own = (uint32_t)b * 64u + (uint32_t)lane;
-  out[k * Q] = weight_f(0) + ST::load(src, own);
+  out[k * Q] = weight_f(0) + ST::load(src, pidx(0, own));
   static_for<1, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     uint32_t slot = pull_slot<i>(lane, b, nbv);
@@ -493,7 +487,7 @@ __global__ void k_sample_pre(StepArgs a, int32_t b0, int32_t nb, uint64_t seed, 
       slot = own;
       plane = kOpp[i];
     }
-    out[k * Q + i] = weight_f(i) + ST::load(src + (size_t)plane * a.S, slot);
+    out[k * Q + i] = weight_f(i) + ST::load(src, pidx(plane, slot));
   });
 }
 

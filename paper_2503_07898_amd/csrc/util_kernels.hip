@@ -14,6 +14,12 @@ __device__ __forceinline__ int64_t canon_of(const SlotArgs &A, int64_t slot) {
   return A.canon ? (int64_t)A.canon[slot] : slot;
 }
 
+// index of population i of a slot: block-interleaved for block layouts,
+// separate planes for the dense lexicographic arm
+__device__ __forceinline__ size_t uidx(const SlotArgs &A, int i, int64_t slot) {
+  return A.blocked ? pidx(i, (uint32_t)slot) : (size_t)i * A.S + (size_t)slot;
+}
+
 // FP64 equilibrium, shifted: f^eq_i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
 template <class ST>
 __global__ void k_init_eq(SlotArgs A, const double *rho, const double *u) {
@@ -24,8 +30,8 @@ __global__ void k_init_eq(SlotArgs A, const double *rho, const double *u) {
   T *pa = (T *)A.pop_a, *pb = (T *)A.pop_b;
   if (c < 0) {
     for (int i = 0; i < Q; ++i) {
-      pa[(size_t)i * A.S + slot] = ST::from_double(0.0);
-      pb[(size_t)i * A.S + slot] = ST::from_double(0.0);
+      pa[uidx(A, i, slot)] = ST::from_double(0.0);
+      pb[uidx(A, i, slot)] = ST::from_double(0.0);
     }
     return;
   }
@@ -35,8 +41,8 @@ __global__ void k_init_eq(SlotArgs A, const double *rho, const double *u) {
     const double cu = kCx[i] * ux + kCy[i] * uy + kCz[i] * uz;
     const double h = weight_d(i) * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
     const T v = ST::from_double(h);
-    pa[(size_t)i * A.S + slot] = v;
-    pb[(size_t)i * A.S + slot] = v;
+    pa[uidx(A, i, slot)] = v;
+    pb[uidx(A, i, slot)] = v;
   }
 }
 
@@ -50,7 +56,7 @@ __global__ void k_read_macro(SlotArgs A, void *rho_out, void *u_out, int f64) {
   const T *p = (const T *)A.pop_a;
   double d = 0, jx = 0, jy = 0, jz = 0;
   for (int i = 0; i < Q; ++i) {
-    const double h = ST::to_double(p[(size_t)i * A.S + slot]);
+    const double h = ST::to_double(p[uidx(A, i, slot)]);
     d += h;
     jx += kCx[i] * h;
     jy += kCy[i] * h;
@@ -80,7 +86,7 @@ __global__ void k_read_pop(SlotArgs A, double *f) {
   const int64_t c = canon_of(A, slot);
   if (c < 0) return;
   const T *p = (const T *)A.pop_a;
-  for (int i = 0; i < Q; ++i) f[(size_t)i * A.n + c] = weight_d(i) + ST::to_double(p[(size_t)i * A.S + slot]);
+  for (int i = 0; i < Q; ++i) f[(size_t)i * A.n + c] = weight_d(i) + ST::to_double(p[uidx(A, i, slot)]);
 }
 
 template <class ST>
@@ -91,7 +97,7 @@ __global__ void k_write_pop(SlotArgs A, const double *f) {
   const int64_t c = canon_of(A, slot);
   if (c < 0) return;
   T *p = (T *)A.pop_a;
-  for (int i = 0; i < Q; ++i) p[(size_t)i * A.S + slot] = ST::from_double(f[(size_t)i * A.n + c] - weight_d(i));
+  for (int i = 0; i < Q; ++i) p[uidx(A, i, slot)] = ST::from_double(f[(size_t)i * A.n + c] - weight_d(i));
 }
 
 // Per 64-slot row partial sums: mass, momentum, kinetic energy, times weight.
@@ -107,7 +113,7 @@ __global__ __launch_bounds__(64) void k_reduce_partial(SlotArgs A, double weight
     const T *p = (const T *)A.pop_a;
     double d = 0, jx = 0, jy = 0, jz = 0;
     for (int i = 0; i < Q; ++i) {
-      const double h = ST::to_double(p[(size_t)i * A.S + slot]);
+      const double h = ST::to_double(p[uidx(A, i, slot)]);
       d += h;
       jx += kCx[i] * h;
       jy += kCy[i] * h;

@@ -145,6 +145,7 @@ def test_closure_judge_threshold(orc, mlp):
     judge = 0 accepts both."""
     p = make_params(mlp)
     p.in_std[:] = 1e3  # inputs far inside the range limit
+    p.out_std[:] = 1e-12  # a negligible absolute floor
     f = sample_populations(orc, 10, 6)
     t = mlp.regularized_target(f)
     for scale, judge, expect_fall in ((1.005, 0.01, False), (1.02, 0.01, True), (1.02, 0.0, False)):
@@ -154,3 +155,21 @@ def test_closure_judge_threshold(orc, mlp):
             rho = f.sum(-1)
             feq = np.array([orc.equilibrium(*orc.moments(fk)) for fk in f])
             assert np.allclose(out, feq + (1 - 1 / 0.51) * rho[:, None] * t * scale, atol=1e-15, rtol=0)
+
+
+def test_closure_judge_floor_near_equilibrium(orc, mlp):
+    """At equilibrium f1 = 0: an output deviating by less than judge x floor
+    (floor = |out_std|, the typical target size) is kept, a larger one falls
+    back."""
+    p = make_params(mlp)
+    p.in_std[:] = 1e3
+    p.out_std[:] = 1e-3
+    f = np.array([orc.equilibrium(1.0 + 0.01 * k, [0.02, -0.01, 0.005 * k]) for k in range(5)])
+    c, w = mlp.lattice()
+    Qt = mlp.hermite_tensors()
+    y = 4.5 * w * np.einsum("iab,ab->i", Qt, np.diag([1.0, -1.0, 0.0]))  # a pure stress direction
+    lim = 0.01 * np.sqrt(np.sum(p.out_std ** 2))
+    for size, expect_fall in ((0.5 * lim, False), (2.0 * lim, True)):
+        yo = np.tile(y / np.linalg.norm(y) * size, (len(f), 1))
+        _, fell = mlp.collide(p, f, 0.6, y_override=yo)
+        assert (fell == expect_fall).all(), size
