@@ -19,6 +19,7 @@ inline namespace LBM_LATTICE_NS {
 struct StoreF32 {
   using T = float;
   static __device__ __forceinline__ float load(const T *p, size_t i) { return p[i]; }
+  static __device__ __forceinline__ float decode(T v) { return v; }
   static __device__ __forceinline__ void store(T *p, size_t i, float v) {
     __builtin_nontemporal_store(v, p + i);
   }
@@ -42,6 +43,7 @@ struct StoreF16 {
   static __device__ __forceinline__ float load(const T *p, size_t i) {
     return (float)__builtin_bit_cast(_Float16, p[i]);
   }
+  static __device__ __forceinline__ float decode(T v) { return (float)__builtin_bit_cast(_Float16, v); }
   static __device__ __forceinline__ void store(T *p, size_t i, float v) {
     __builtin_nontemporal_store(f16_rne(v), p + i);
   }
@@ -65,6 +67,7 @@ struct StoreBF16 {
   static __device__ __forceinline__ float load(const T *p, size_t i) {
     return __uint_as_float((uint32_t)p[i] << 16);
   }
+  static __device__ __forceinline__ float decode(T v) { return __uint_as_float((uint32_t)v << 16); }
   static __device__ __forceinline__ void store(T *p, size_t i, float v) {
     __builtin_nontemporal_store(bf16_rne(v), p + i);
   }

@@ -354,16 +354,25 @@ __global__ __launch_bounds__(256) void k_block_collide(StepArgs a, int32_t g0, i
 // of 8 such entries whose mean is taken (coalescence onto the 2x2x2
 // footprint of a coarse voxel).  Explosion, re-entry and coalescence are all
 // gathers, so no atomics and no second pass are needed.
+// The five source buffers come in as wave-uniform values held in scalar
+// registers, and the per-lane choice is a chain of selects between them (an
+// indexed read of the argument block would add a dependent memory load to
+// every gather).
+template <class T>
+struct MrBases {
+  const __attribute__((address_space(1))) T *p[5];  // global memory
+};
+
 template <class ST>
-__device__ __forceinline__ float mr_fetch(const MrArgs &m, uint32_t e, int plane, int opp_plane) {
+__device__ __forceinline__ float mr_fetch(const MrBases<typename ST::T> &mb, uint32_t e, int plane, int opp_plane) {
   using T = typename ST::T;
   const uint32_t tag = e >> 29;
   const uint32_t slot = e & ((1u << 28) - 1u);
   const int pl = (e >> 28) & 1u ? opp_plane : plane;
-  const T *base = (const T *)m.src[0];
+  const __attribute__((address_space(1))) T *base = mb.p[0];
 #pragma unroll
-  for (int t = 1; t < 5; ++t) base = tag == (uint32_t)t ? (const T *)m.src[t] : base;
-  return ST::load(base, pidx(pl, slot));
+  for (int t = 1; t < 5; ++t) base = tag == (uint32_t)t ? mb.p[t] : base;
+  return ST::decode(base[pidx(pl, slot)]);
 }
 
 template <class ST, int COLL, bool FUSED>
@@ -376,18 +385,28 @@ __global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g
   T *__restrict__ dst = (T *)a.dst;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
   const uint32_t *tab = m.jtab + ((size_t)b * 2 + m.phase) * Q * 64 + lane;
+  MrBases<T> mb;
+#pragma unroll
+  for (int t = 0; t < 5; ++t) mb.p[t] = (const __attribute__((address_space(1))) T *)(const T *)m.src[t];
   float h[Q];
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     const uint32_t e = tab[i * 64];
     if ((e >> 29) == 7u) {
-      const uint32_t *lst = m.jlist + (size_t)(e & ((1u << 28) - 1u)) * 8;
-      float sum = mr_fetch<ST>(m, lst[0], i, kOpp[i]);
+      // the 8 entries (32 bytes, 32-byte aligned) in two loads, then the 8
+      // gathers issued together, then the sum in a fixed order
+      const uint4 *lst = (const uint4 *)(m.jlist + (size_t)(e & ((1u << 28) - 1u)) * 8);
+      const uint4 e0 = lst[0], e1 = lst[1];
+      const uint32_t ent[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
+      float v[8];
 #pragma unroll
-      for (int k = 1; k < 8; ++k) sum = sum + mr_fetch<ST>(m, lst[k], i, kOpp[i]);
+      for (int k = 0; k < 8; ++k) v[k] = mr_fetch<ST>(mb, ent[k], i, kOpp[i]);
+      float sum = v[0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) sum = sum + v[k];
       h[i] = sum * 0.125f;
     } else {
-      h[i] = mr_fetch<ST>(m, e, i, kOpp[i]);
+      h[i] = mr_fetch<ST>(mb, e, i, kOpp[i]);
     }
   });
   if constexpr (FUSED) collide<COLL>(h, a.omega);
