@@ -133,7 +133,6 @@ template <class ST, bool MASKED>
 __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t g0, int32_t n) {
   using T = typename ST::T;
   __shared__ __attribute__((aligned(16))) __bf16 wl[kWPackedElems];
-  __shared__ __attribute__((aligned(16))) __bf16 act[4][64 * kActStride];
   stage_weights(wl, (const __bf16 *)a.mlp_w);
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6;
@@ -182,7 +181,7 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
     out_of_range = out_of_range || fabsf(x[i]) > 8.0f;
   }
   float y[Q];
-  mlp_forward_wave(x, y, act[wave], wl, a.mlp_bias, lane);
+  mlp_forward_wave_reg(x, y, wl, a.mlp_bias, lane);
 #pragma unroll
   for (int i = 0; i < Q; ++i) y[i] = fmaf(y[i], sd[64 + i], sd[96 + i]);
   project_out(y);
@@ -388,25 +387,36 @@ __global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g
   MrBases<T> mb;
 #pragma unroll
   for (int t = 0; t < 5; ++t) mb.p[t] = (const __attribute__((address_space(1))) T *)(const T *)m.src[t];
+  // three rounds of independent loads: the table entries, the direct
+  // gathers, then the coalescence lists
+  uint32_t e[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) e[i] = tab[i * 64];
   float h[Q];
   static_for<0, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    const uint32_t e = tab[i * 64];
-    if ((e >> 29) == 7u) {
-      // the 8 entries (32 bytes, 32-byte aligned) in two loads, then the 8
-      // gathers issued together, then the sum in a fixed order
-      const uint4 *lst = (const uint4 *)(m.jlist + (size_t)(e & ((1u << 28) - 1u)) * 8);
-      const uint4 e0 = lst[0], e1 = lst[1];
-      const uint32_t ent[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
-      float v[8];
+    // a lane with a list entry reads slot 0 of the first buffer here (a
+    // valid address) and takes its list mean below
+    h[i] = mr_fetch<ST>(mb, (e[i] >> 29) == 7u ? 0u : e[i], i, kOpp[i]);
+  });
+  static_for<0, Q>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const bool list = (e[i] >> 29) == 7u;
+    if (__builtin_amdgcn_ballot_w64(list) != 0) {
+      if (list) {
+        // the 8 entries (32 bytes, 32-byte aligned) in two loads, the 8
+        // gathers together, then the sum in a fixed order
+        const uint4 *lst = (const uint4 *)(m.jlist + (size_t)(e[i] & ((1u << 28) - 1u)) * 8);
+        const uint4 e0 = lst[0], e1 = lst[1];
+        const uint32_t ent[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
+        float v[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = mr_fetch<ST>(mb, ent[k], i, kOpp[i]);
-      float sum = v[0];
+        for (int k = 0; k < 8; ++k) v[k] = mr_fetch<ST>(mb, ent[k], i, kOpp[i]);
+        float sum = v[0];
 #pragma unroll
-      for (int k = 1; k < 8; ++k) sum = sum + v[k];
-      h[i] = sum * 0.125f;
-    } else {
-      h[i] = mr_fetch<ST>(mb, e, i, kOpp[i]);
+        for (int k = 1; k < 8; ++k) sum = sum + v[k];
+        h[i] = sum * 0.125f;
+      }
     }
   });
   if constexpr (FUSED) collide<COLL>(h, a.omega);
