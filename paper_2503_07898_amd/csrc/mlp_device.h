@@ -69,11 +69,14 @@ struct MlpView {
 
 // tanh-form GELU, written as x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3))
 __device__ __forceinline__ float gelu_f(float x) {
-  const float k2 = 2.0f * 0.7978845608028654f;
-  const float z = k2 * fmaf(0.044715f * x, x * x, x);
-  // x * sigmoid(2z) with the hardware reciprocal (about 1 ulp; the result
-  // is rounded to bf16 for the next layer) instead of an IEEE division
-  return x * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+  // exp(-2z) = 2^(x (c1 + c2 x^2)), z = sqrt(2/pi) (x + 0.044715 x^3):
+  // c1 = -2 sqrt(2/pi) / ln 2, c2 = 0.044715 c1; then x * sigmoid(2z) with
+  // the hardware exp2 and reciprocal (about 1 ulp each; the result is
+  // rounded to bf16 for the next layer)
+  constexpr float c1 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
+  constexpr float c2 = 0.044715f * c1;
+  const float e = __builtin_amdgcn_exp2f(x * fmaf(c2, x * x, c1));
+  return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
 // derivative of gelu_f
@@ -180,6 +183,145 @@ __device__ __forceinline__ void mlp_forward_wave(const float (&x)[Q], float (&yt
 #pragma unroll
   for (int i = 0; i < Q; ++i) yt[i] = out[lane * kOutStride + i];
   wave_lds_sync();
+}
+
+// ----------------------------------------------- register-resident forward --
+// Inference form of the same network with no activation traffic through LDS.
+// The product is taken transposed, Z^T = W^T X^T: the weights are the A
+// operand (their packed order is already the A order of W^T) and the 64
+// voxels of the wave form two 32-wide B / D column tiles.  A lane then holds,
+// in accumulator element r of tile (m, t), feature 32m + 8(r/4) + 4h + r%4 of
+// voxel 32t + l%32 (h = lane / 32).  The next layer's B operand needs, per
+// 16-feature chunk, features 8h..8h+7 of that voxel: each lane already has
+// half of them, and one v_permlane32_swap per register pair exchanges the
+// other half with lane l ^ 32.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// swap the upper 32 lanes of x with the lower 32 lanes of y
+__device__ __forceinline__ void swap_halves(uint32_t &x, uint32_t &y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+
+// bias of accumulator element r (feature 32m + 8(r/4) + 4h + r%4)
+__device__ __forceinline__ void bias_init(f32x16_t &acc, const float *bias, int m, int h) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 b4 = *(const float4 *)(bias + 32 * m + 8 * q + 4 * h);
+    acc[4 * q + 0] = b4.x;
+    acc[4 * q + 1] = b4.y;
+    acc[4 * q + 2] = b4.z;
+    acc[4 * q + 3] = b4.w;
+  }
+}
+
+// B operands (two voxel tiles) of one 16-feature chunk c of a hidden layer
+// from the GELU'd accumulators of feature tile c/2.
+__device__ __forceinline__ void hidden_chunk(const f32x16_t &z0, const f32x16_t &z1, int c, bf16x8_t &b0,
+                                             bf16x8_t &b1) {
+  const int r0 = 8 * (c & 1);
+  uint32_t x[2][2], y[2][2];  // [tile][dword]
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    x[0][k] = pack_bf16(gelu_f(z0[r0 + 2 * k]), gelu_f(z0[r0 + 2 * k + 1]));
+    y[0][k] = pack_bf16(gelu_f(z0[r0 + 4 + 2 * k]), gelu_f(z0[r0 + 4 + 2 * k + 1]));
+    x[1][k] = pack_bf16(gelu_f(z1[r0 + 2 * k]), gelu_f(z1[r0 + 2 * k + 1]));
+    y[1][k] = pack_bf16(gelu_f(z1[r0 + 4 + 2 * k]), gelu_f(z1[r0 + 4 + 2 * k + 1]));
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) swap_halves(x[t][k], y[t][k]);
+  const u32x4_t w0 = {x[0][0], x[0][1], y[0][0], y[0][1]};
+  const u32x4_t w1 = {x[1][0], x[1][1], y[1][0], y[1][1]};
+  b0 = __builtin_bit_cast(bf16x8_t, w0);
+  b1 = __builtin_bit_cast(bf16x8_t, w1);
+}
+
+// One output tile m of a layer: acc[t] = W^T[m] B[t] + bias over KC chunks
+// of 16 inputs; bk[c][t] are the B operands of chunk c.
+template <int KC, int MT>
+__device__ __forceinline__ void layer_tile(const __bf16 *wl, const float *bias, const bf16x8_t (&bk)[KC][2],
+                                           int m, f32x16_t (&acc)[2], int lane) {
+  bias_init(acc[0], bias, m, lane >> 5);
+  acc[1] = acc[0];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const bf16x8_t a = *(const bf16x8_t *)(wl + ((c * MT + m) * 64 + lane) * 8);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bk[c][t], acc[t], 0, 0, 0);
+  }
+}
+
+// Network forward of the wave's 64 voxels (lane v brings voxel v's 19
+// standardized inputs x and receives its 19 raw outputs yt), weights packed
+// in LDS (wl), biases b1|b2|b3 in global memory.
+__device__ __forceinline__ void mlp_forward_wave_reg(const float (&x)[Q], float (&yt)[Q], const __bf16 *wl,
+                                                     const float *bias, int lane) {
+  // layer 1 operands: chunk c holds features 16c..16c+15; the lane's own
+  // features 16c..16c+7 (F0) and 16c+8..16c+15 (F1) are swapped across
+  // halves so that F0-slot registers form tile 0 and F1-slot registers tile 1
+  bf16x8_t b1[2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    uint32_t f0[4], f1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i0 = 16 * c + 2 * k, i1 = 16 * c + 8 + 2 * k;
+      f0[k] = pack_bf16(i0 < Q ? x[i0] : 0.0f, i0 + 1 < Q ? x[i0 + 1] : 0.0f);
+      f1[k] = pack_bf16(i1 < Q ? x[i1] : 0.0f, i1 + 1 < Q ? x[i1 + 1] : 0.0f);
+      swap_halves(f0[k], f1[k]);
+    }
+    const u32x4_t w0 = {f0[0], f0[1], f0[2], f0[3]};
+    const u32x4_t w1 = {f1[0], f1[1], f1[2], f1[3]};
+    b1[c][0] = __builtin_bit_cast(bf16x8_t, w0);
+    b1[c][1] = __builtin_bit_cast(bf16x8_t, w1);
+  }
+  // hidden layers one 32-feature tile at a time, each tile turned into the
+  // next layer's two 16-feature chunks right away
+  bf16x8_t b2[4][2], b3[4][2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    f32x16_t z[2];
+    layer_tile<2, 2>(wl, bias, b1, m, z, lane);
+    hidden_chunk(z[0], z[1], 2 * m, b2[2 * m][0], b2[2 * m][1]);
+    hidden_chunk(z[0], z[1], 2 * m + 1, b2[2 * m + 1][0], b2[2 * m + 1][1]);
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    f32x16_t z[2];
+    layer_tile<4, 2>(wl + kW1Elems, bias + kMlpHidden, b2, m, z, lane);
+    hidden_chunk(z[0], z[1], 2 * m, b3[2 * m][0], b3[2 * m][1]);
+    hidden_chunk(z[0], z[1], 2 * m + 1, b3[2 * m + 1][0], b3[2 * m + 1][1]);
+  }
+  f32x16_t o[1][2];
+  layer_tile<4, 1>(wl + kW1Elems + kW2Elems, bias + 2 * kMlpHidden, b3, 0, o[0], lane);
+  // gather the voxel's outputs: element r (= 4q + r%4) of tile t holds
+  // output 8q + 4h + r%4 of voxel 32t + l%32, so each lane keeps the half of
+  // its own voxel's outputs it holds and receives the other half from lane
+  // l ^ 32 (a lane shuffle: a 32-lane swap of accumulator elements was
+  // merged into one by the compiler)
+  const bool lo = lane < 32;
+  float ox[11], oy[11];
+#pragma unroll
+  for (int r = 0; r < 11; ++r) {
+    const float give = lo ? o[0][1][r] : o[0][0][r];
+    const float recv = __shfl_xor(give, 32, 64);
+    ox[r] = lo ? o[0][0][r] : recv;  // outputs 8q + r%4
+    oy[r] = lo ? recv : o[0][1][r];  // outputs 8q + 4 + r%4
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int r = 4 * (i / 8) + (i & 3);
+    yt[i] = (i & 4) ? oy[r] : ox[r];
+  }
 }
 
 // Copies the packed weights (16 KB) from global memory to LDS; every thread
