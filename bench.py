@@ -165,7 +165,8 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--arms", default="all", choices=["all", "none"])
+    ap.add_argument("--arms", default="all", choices=["all", "none", "closure"],
+                    help="closure: only the learned-closure arms (for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (torch) 5 times, the reference "
@@ -229,7 +230,7 @@ def main(argv=None) -> int:
     torch.cuda.empty_cache()
 
     arms = {}
-    if args.arms == "all":
+    if args.arms in ("all", "closure"):
         def arm(name, make, steps, bytes_per_update, interior=False):
             log(name)
             gg = make()
@@ -253,6 +254,7 @@ def main(argv=None) -> int:
             gg.close()
             torch.cuda.empty_cache()
 
+    if args.arms == "all":
         arm("cavity256_f32_plain_lexicographic", lambda: cases.cavity(schedule=lbm.PLAIN_SINGLE_KERNEL), 100, 152)
         arm("cavity256_f16_disagg", lambda: cases.cavity(storage=lbm.F16_SHIFTED), 100, 76)
         arm("cavity256_bf16_disagg", lambda: cases.cavity(storage=lbm.BF16_SHIFTED), 100, 76)
@@ -283,6 +285,8 @@ def main(argv=None) -> int:
         arm("taylor_green256_re1600_f32_regularized",
             lambda: cases.taylor_green(collision=lbm.REGULARIZED), 100, 152)
         arm("taylor_green256_re1600_f32_bgk", lambda: cases.taylor_green(collision=lbm.BGK), 100, 152)
+
+    if args.arms in ("all", "closure"):
         # the learned closure in place of the collision operator
         net, which = closure_net(torch, lbm, workloads, cases)
 
