@@ -699,7 +699,7 @@ lbm_status lbm_mlp_bind(lbm_mlp *m, void *dev, size_t bytes, void *stream) {
   B.wpacked = m->ws + m->off_w;
   B.bias = (float *)(m->ws + m->off_bias);
   B.stdz = (float *)(m->ws + m->off_stdz);
-  B.fallbacks = (unsigned int *)(m->ws + m->off_fb);
+  B.fallbacks = (unsigned long long *)(m->ws + m->off_fb);
   B.save = (float *)(m->ws + m->off_save);
   B.dyt = (float *)(m->ws + m->off_dyt);
   B.dz1 = (float *)(m->ws + m->off_dz1);
@@ -815,12 +815,12 @@ lbm_status lbm_mlp_fallbacks(lbm_mlp *m, uint64_t *count, int32_t reset, void *s
   if (!m || !count) return fail(LBM_ERR_INVALID_ARG, "null argument");
   if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
   hipStream_t s = (hipStream_t)stream;
-  uint32_t c = 0;
-  hipError_t e = hipMemcpyAsync(&c, m->B.fallbacks, 4, hipMemcpyDeviceToHost, s);
+  uint64_t c = 0;
+  hipError_t e = hipMemcpyAsync(&c, m->B.fallbacks, sizeof c, hipMemcpyDeviceToHost, s);
   if (!e) e = hipStreamSynchronize(s);
   if (!e && reset) {
-    const uint32_t z = 0;
-    e = hipMemcpyAsync(m->B.fallbacks, &z, 4, hipMemcpyHostToDevice, s);
+    const uint64_t z = 0;
+    e = hipMemcpyAsync(m->B.fallbacks, &z, sizeof z, hipMemcpyHostToDevice, s);
     if (!e) e = hipStreamSynchronize(s);
   }
   if (e) return hip_fail(e, "mlp_fallbacks");

@@ -32,7 +32,7 @@ struct StepArgs {
   const void *mlp_w;              // packed bf16 weights
   const float *mlp_bias;          // b1 | b2 | b3
   const float *mlp_stdz;          // in_mean | in_inv_std | out_std | out_mean (32 each)
-  unsigned int *mlp_fallbacks;    // voxels that fell back to the regularized operator
+  unsigned long long *mlp_fallbacks;  // voxels that fell back to the regularized operator (64-bit)
   float mlp_judge;                // relative L2 tolerance against the regularized f1 (0 = off)
   // bitmask-based grouping
   const uint32_t *bbits;          // [(nblocks+31)/32] bit set = boundary block
@@ -79,7 +79,7 @@ struct MlpBuffers {
   void *wpacked;      // packed bf16 weights
   float *bias;        // b1 | b2 | b3 (padded)
   float *stdz;        // standardization, 4 x 32
-  unsigned int *fallbacks;
+  unsigned long long *fallbacks;
   float *save;        // [batch_max][288] forward intermediates
   float *dyt;         // [batch_max][19]
   float *dz1;         // [batch_max][64]

@@ -64,7 +64,7 @@ struct MlpView {
   const __bf16 *w;         // packed weights (global), kWPackedElems
   const float *bias;       // b1 [64], b2 [64], b3 [32] (global)
   const float *stdz;       // in_mean, in_inv_std, out_std, out_mean, 32 each
-  unsigned int *fallbacks;  // fallback counter
+  unsigned long long *fallbacks;  // fallback counter (64-bit: a long run exceeds 2^32 updates)
 };
 
 // tanh-form GELU, written as x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3))

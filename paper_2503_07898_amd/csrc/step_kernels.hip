@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
 #pragma unroll
     for (int i = 0; i < Q; ++i) h[i] = hs[i];
   const uint64_t bal = __ballot(fb);
-  if (lane == 0 && bal) atomicAdd(a.mlp_fallbacks, (unsigned int)__popcll(bal));
+  if (lane == 0 && bal) atomicAdd(a.mlp_fallbacks, (unsigned long long)__popcll(bal));
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dst, pidx(i, own_slot), h[i]);
 }

@@ -66,6 +66,7 @@ def oracle_curve(orc, n, tau, rho0, u0, checkpoints, keep, out):
         r = r.reshape(-1)
         v = v.reshape(-1, 3)
         out[s] = (kinetic_energy(r, v), v.copy() if s in keep else None)
+        _say(f"  FP64 oracle reached step {s}")
 
 
 def gpu_arm(n, tau, rho0, u0, checkpoints, keep, collision, net=None, judge=0.01):
