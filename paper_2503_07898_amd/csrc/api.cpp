@@ -144,6 +144,11 @@ StepArgs level_args(const lbm_grid *g, const LevelRT &r) {
   return a;
 }
 
+// Multires levels up to this many blocks run each update as one launch:
+// 8,192 waves fill the chip at eight waves per SIMD, so a smaller level's
+// launches are bound by their dispatch and drain, not by occupancy.
+constexpr int64_t kMergeMaxBlocks = 8192;
+
 // Launches of one level update with the level's current buffer roles.
 void level_update(const lbm_grid *g, const std::vector<LevelRT> &lv, int l, int substep,
                   std::vector<Launch> &out) {
@@ -173,7 +178,7 @@ void level_update(const lbm_grid *g, const std::vector<LevelRT> &lv, int l, int 
     x.first = f0;
     x.count = n;
     x.args = a;
-    if (kind == kKernelJump) {
+    if (kind == kKernelJump || kind == kKernelLevelMerged) {
       MrArgs &m = x.mr;
       const LevelRT *fr = l > 0 ? &lv[l - 1] : nullptr;
       const LevelRT *cr = l + 1 < (int)lv.size() ? &lv[l + 1] : nullptr;
@@ -206,18 +211,34 @@ void level_update(const lbm_grid *g, const std::vector<LevelRT> &lv, int l, int 
     }
     return;
   }
+  // a level with fewer blocks than the chip holds waves at once runs its
+  // independent group kernels as one launch (the closure keeps its own
+  // kernels)
+  const bool merge = nb <= kMergeMaxBlocks && g->collision != LBM_MLP;
+  auto push_merged = [&](int32_t fused) {
+    push(kKernelLevelMerged, fused, 0, nb);
+    for (int k = 0; k < 4; ++k) out.back().gcount[k] = (int32_t)gc[k];
+  };
   if (plain && l > 0) {
     // unfused baseline: streaming kernels, then collision in place
-    push(kKernelJump, 0, first[0], (int32_t)gc[0]);
-    push(kKernelBoundary, 0, first[1], (int32_t)gc[1]);
-    push(kKernelMasked, 0, first[2], (int32_t)gc[2]);
-    push(kKernelFull, 0, first[3], (int32_t)gc[3]);
+    if (merge) {
+      push_merged(0);
+    } else {
+      push(kKernelJump, 0, first[0], (int32_t)gc[0]);
+      push(kKernelBoundary, 0, first[1], (int32_t)gc[1]);
+      push(kKernelMasked, 0, first[2], (int32_t)gc[2]);
+      push(kKernelFull, 0, first[3], (int32_t)gc[3]);
+    }
     push(kKernelCollide, 1, first[0], (int32_t)gc[0]);
     push(kKernelCollideHeavy, 1, first[1], (int32_t)gc[1]);
     push(kKernelCollide, 1, first[2], (int32_t)(gc[2] + gc[3]));
     return;
   }
   // fused collide-and-stream on every group (the jump group through its tables)
+  if (merge) {
+    push_merged(1);
+    return;
+  }
   push(kKernelFull, 1, first[3], (int32_t)gc[3]);
   push(kKernelMasked, 1, first[2], (int32_t)gc[2]);
   push(kKernelBoundary, 1, first[1], (int32_t)gc[1]);

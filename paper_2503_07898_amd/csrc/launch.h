@@ -49,7 +49,8 @@ enum KernelKind : int32_t {
   kKernelCollideHeavy = 5,  // collision only for heavy-boundary blocks
   kKernelLex = 6,           // dense lexicographic single kernel
   kKernelInteriorBits = 7,  // bitmask grouping: all blocks, non-boundary ones processed
-  kKernelBoundaryBits = 8   // bitmask grouping: all blocks, boundary ones processed
+  kKernelBoundaryBits = 8,  // bitmask grouping: all blocks, boundary ones processed
+  kKernelLevelMerged = 9    // every group of a small multires level in one launch
 };
 
 // Sources of the multires jump gather, indexed by table tag: own level now,
@@ -66,6 +67,7 @@ struct Launch {
   int32_t kind;
   int32_t fused;          // 0: store the gathered (pre-collision) populations only
   int32_t first, count;   // block range of the launch
+  int32_t gcount[4];      // kKernelLevelMerged: blocks of the jump, boundary, masked, full groups
   StepArgs args;
   MrArgs mr;
 };

@@ -374,12 +374,12 @@ __device__ __forceinline__ float mr_fetch(const MrBases<typename ST::T> &mb, uin
   return ST::decode(base[pidx(pl, slot)]);
 }
 
+constexpr int kJumpGroup = 4;  // directions whose coalescence lists load together
+
+// Per-block body of the jump kernel (b is wave-uniform).
 template <class ST, int COLL, bool FUSED>
-__global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g0, int32_t n) {
+__device__ __forceinline__ void mr_jump_block(const StepArgs &a, const MrArgs &m, int b) {
   using T = typename ST::T;
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
-  if (b >= g0 + n) return;
   const int lane = threadIdx.x & 63;
   T *__restrict__ dst = (T *)a.dst;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
@@ -399,29 +399,92 @@ __global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g
     // valid address) and takes its list mean below
     h[i] = mr_fetch<ST>(mb, (e[i] >> 29) == 7u ? 0u : e[i], i, kOpp[i]);
   });
-  static_for<0, Q>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    const bool list = (e[i] >> 29) == 7u;
-    if (__builtin_amdgcn_ballot_w64(list) != 0) {
-      if (list) {
-        // the 8 entries (32 bytes, 32-byte aligned) in two loads, the 8
-        // gathers together, then the sum in a fixed order
-        const uint4 *lst = (const uint4 *)(m.jlist + (size_t)(e[i] & ((1u << 28) - 1u)) * 8);
-        const uint4 e0 = lst[0], e1 = lst[1];
-        const uint32_t ent[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
-        float v[8];
+  // Coalescence lists, kJumpGroup directions at a time: every lane of a
+  // group with a list in the wave loads list entries (lanes without one
+  // read list 0, which exists then), then all the gathers are issued
+  // together, so a wave waits for two memory round trips per group rather
+  // than two per direction.  The mean is summed in a fixed order.
+  static_for<0, (Q + kJumpGroup - 1) / kJumpGroup>([&](auto gc) {
+    constexpr int i0 = decltype(gc)::value * kJumpGroup;
+    constexpr int G = Q - i0 < kJumpGroup ? Q - i0 : kJumpGroup;
+    bool lst[G];
+    bool any = false;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = mr_fetch<ST>(mb, ent[k], i, kOpp[i]);
-        float sum = v[0];
+    for (int k = 0; k < G; ++k) {
+      lst[k] = (e[i0 + k] >> 29) == 7u;
+      any = any || lst[k];
+    }
+    if (__builtin_amdgcn_ballot_w64(any) != 0) {
+      uint32_t ent[G][8];
 #pragma unroll
-        for (int k = 1; k < 8; ++k) sum = sum + v[k];
-        h[i] = sum * 0.125f;
+      for (int k = 0; k < G; ++k) {
+        const uint32_t li = lst[k] ? (e[i0 + k] & ((1u << 28) - 1u)) : 0u;
+        const uint4 *p = (const uint4 *)(m.jlist + (size_t)li * 8);
+        const uint4 ea = p[0], eb = p[1];
+        ent[k][0] = ea.x; ent[k][1] = ea.y; ent[k][2] = ea.z; ent[k][3] = ea.w;
+        ent[k][4] = eb.x; ent[k][5] = eb.y; ent[k][6] = eb.z; ent[k][7] = eb.w;
+      }
+      float v[G][8];
+#pragma unroll
+      for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[k][j] = mr_fetch<ST>(mb, ent[k][j], i0 + k, kOpp[i0 + k]);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        float sum = v[k][0];
+#pragma unroll
+        for (int j = 1; j < 8; ++j) sum = sum + v[k][j];
+        if (lst[k]) h[i0 + k] = sum * 0.125f;
       }
     }
   });
   if constexpr (FUSED) collide<COLL>(h, a.omega);
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dst, pidx(i, own_slot), h[i]);
+}
+
+template <class ST, int COLL, bool FUSED>
+__global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g0, int32_t n) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
+  if (b >= g0 + n) return;
+  mr_jump_block<ST, COLL, FUSED>(a, m, b);
+}
+
+// One launch for all groups of a small multires level update: the groups
+// are independent within the update, and a level that holds fewer blocks
+// than the chip holds waves is bound by the dispatch and drain of each
+// launch rather than by occupancy.  Workgroups take the groups in storage
+// order [jump | boundary | masked | full] (cnt[g] blocks each, four per
+// workgroup); consecutive workgroups go to different XCDs, which spreads
+// every group over the whole chip.  Each block runs the body of its
+// group's own kernel.
+template <class ST, int COLL, bool FUSED>
+__global__ __launch_bounds__(256) void k_level_merged(StepArgs a, MrArgs m, int32_t nj, int32_t nbd, int32_t nm,
+                                                      int32_t nf) {
+  const int wave = (int)(threadIdx.x >> 6);
+  int k = (int)blockIdx.x;
+  const int wj = (nj + 3) >> 2, wb = (nbd + 3) >> 2, wm = (nm + 3) >> 2;
+  if (k < wj) {
+    const int b = __builtin_amdgcn_readfirstlane(k * 4 + wave);
+    if (b < nj) mr_jump_block<ST, COLL, FUSED>(a, m, b);
+    return;
+  }
+  k -= wj;
+  if (k < wb) {
+    const int b = __builtin_amdgcn_readfirstlane(k * 4 + wave);
+    if (b < nbd) boundary_block<ST, COLL, FUSED, false>(a, nj + b);
+    return;
+  }
+  k -= wb;
+  if (k < wm) {
+    const int b = __builtin_amdgcn_readfirstlane(k * 4 + wave);
+    if (b < nm) interior_block<ST, COLL, true, FUSED>(a, nj + nbd + b);
+    return;
+  }
+  k -= wm;
+  const int b = __builtin_amdgcn_readfirstlane(k * 4 + wave);
+  if (b < nf) interior_block<ST, COLL, false, FUSED>(a, nj + nbd + nm + b);
 }
 
 #endif  // LBM_Q27
@@ -566,6 +629,14 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
       if (f) hipLaunchKernelGGL((k_mr_jump<ST, COLL, true>), grd, blk, 0, s, L.args, L.mr, g0, n);
       else hipLaunchKernelGGL((k_mr_jump<ST, COLL, false>), grd, blk, 0, s, L.args, L.mr, g0, n);
       break;
+    case kKernelLevelMerged: {
+      const int32_t *c = L.gcount;
+      const dim3 gm((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4);
+      if (g0 != 0 || c[0] + c[1] + c[2] + c[3] != n) return hipErrorInvalidValue;
+      if (f) hipLaunchKernelGGL((k_level_merged<ST, COLL, true>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
+      else hipLaunchKernelGGL((k_level_merged<ST, COLL, false>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
+      break;
+    }
 #endif
     case kKernelCollide:
       hipLaunchKernelGGL((k_block_collide<ST, COLL, false>), grd, blk, 0, s, L.args, g0, n);
@@ -604,6 +675,7 @@ hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipSt
 #else
     // the closure runs on the non-boundary groups; every other kernel uses
     // the regularized operator it was trained to imitate
+    if (L.kind == kKernelLevelMerged) return hipErrorInvalidValue;  // never scheduled with the closure
     if (L.fused && (L.kind == kKernelFull || L.kind == kKernelMasked)) {
       switch (storage) {
         case LBM_F32: return launch_mlp<StoreF32>(L, s);
