@@ -289,6 +289,16 @@ lbm_status lbm_mlp_destroy(lbm_mlp *m);
  * regularized operator.  The closure must outlive its use by the grid. */
 lbm_status lbm_set_collision(lbm_grid *g, lbm_collision c, const lbm_mlp *m);
 
+/* Launch shape of multires level updates (a tuning knob; results are bit
+ * for bit the same either way).  The groups of one level update are
+ * independent (section on multi-resolution kernel fusion), so a level with
+ * at most max_blocks blocks runs all of them as one launch; larger levels
+ * launch one kernel per group.  Default 8192 (the chip's wave slots at
+ * eight waves per SIMD); 0 keeps one launch per group everywhere.  Dense
+ * and block-sparse grids always launch per group.  Any grid state; takes
+ * effect at the next step.  max_blocks < 0 is LBM_ERR_INVALID_ARG. */
+lbm_status lbm_set_merge_limit(lbm_grid *g, int64_t max_blocks);
+
 /* n pre-collision population sets (FP32, unshifted, [n][19]: the values the
  * collision operator of the next step receives, pulled from the current
  * post-collision field with bounce-back) of fluid voxels drawn uniformly

@@ -87,9 +87,16 @@ struct LatticeLaunchers {
         &ns::launch_reduce_final                                                                      \
   }
 
+// Multires levels up to this many blocks run each update as one launch by
+// default: 8,192 waves fill the chip at eight waves per SIMD, so a smaller
+// level's separate group launches are bound by their dispatch and drain,
+// not by occupancy.
+constexpr int64_t kMergeMaxBlocks = 8192;
+
 struct lbm_grid {
   lbm_grid_desc desc{};
   int32_t q = 19;  // lattice
+  int64_t merge_max = kMergeMaxBlocks;  // multires: merged level updates up to this many blocks
   LatticeLaunchers ops = LBM_LAUNCHERS_OF(lbm::k19);
   int32_t collision = LBM_BGK;
   const lbm_mlp *mlp = nullptr;
@@ -143,11 +150,6 @@ StepArgs level_args(const lbm_grid *g, const LevelRT &r) {
   }
   return a;
 }
-
-// Multires levels up to this many blocks run each update as one launch:
-// 8,192 waves fill the chip at eight waves per SIMD, so a smaller level's
-// launches are bound by their dispatch and drain, not by occupancy.
-constexpr int64_t kMergeMaxBlocks = 8192;
 
 // Launches of one level update with the level's current buffer roles.
 void level_update(const lbm_grid *g, const std::vector<LevelRT> &lv, int l, int substep,
@@ -214,7 +216,7 @@ void level_update(const lbm_grid *g, const std::vector<LevelRT> &lv, int l, int 
   // a level with fewer blocks than the chip holds waves at once runs its
   // independent group kernels as one launch (the closure keeps its own
   // kernels)
-  const bool merge = nb <= kMergeMaxBlocks && g->collision != LBM_MLP;
+  const bool merge = nb <= g->merge_max && g->collision != LBM_MLP;
   auto push_merged = [&](int32_t fused) {
     push(kKernelLevelMerged, fused, 0, nb);
     for (int k = 0; k < 4; ++k) out.back().gcount[k] = (int32_t)gc[k];
@@ -865,6 +867,13 @@ lbm_status lbm_set_collision(lbm_grid *g, lbm_collision c, const lbm_mlp *m) {
     g->mlp = m;
   }
   g->collision = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_merge_limit(lbm_grid *g, int64_t max_blocks) {
+  if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
+  if (max_blocks < 0) return fail(LBM_ERR_INVALID_ARG, "the merge limit must be >= 0");
+  g->merge_max = max_blocks;
   return LBM_OK;
 }
 

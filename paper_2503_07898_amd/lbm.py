@@ -92,6 +92,7 @@ def lib() -> ctypes.CDLL:
             "lbm_mlp_fallbacks": ([vp, ctypes.POINTER(ctypes.c_uint64), i32, vp], i32),
             "lbm_mlp_destroy": ([vp], i32),
             "lbm_set_collision": ([vp, i32, vp], i32),
+            "lbm_set_merge_limit": ([vp, i64], i32),
             "lbm_sample_populations": ([vp, i32, ctypes.c_uint64, i64, vp, vp], i32),
             "lbm_grid_destroy": ([vp], i32),
         }
@@ -267,6 +268,10 @@ def lbm_set_collision(g, collision: int, mlp=None) -> None:
     check(lib().lbm_set_collision(g, int(collision), mlp))
 
 
+def lbm_set_merge_limit(g, max_blocks: int) -> None:
+    check(lib().lbm_set_merge_limit(g, int(max_blocks)))
+
+
 def lbm_sample_populations(g, level: int, seed: int, n: int, f_ptr: int, stream=None) -> None:
     check(lib().lbm_sample_populations(g, int(level), ctypes.c_uint64(seed), int(n), f_ptr, _stream_ptr(stream)))
 
@@ -390,6 +395,9 @@ class Grid:
     def set_collision(self, collision: int, mlp=None) -> None:
         self._mlp_keep = mlp
         lbm_set_collision(self.h, collision, None if mlp is None else mlp.h)
+
+    def set_merge_limit(self, max_blocks: int) -> None:
+        lbm_set_merge_limit(self.h, max_blocks)
 
     def sample(self, seed: int, n: int, level: int = 0):
         import torch

@@ -238,6 +238,33 @@ def test_launch_structure_bitmask_grouping():
                  level_map=np.zeros(n[::-1], np.uint8), device="cpu")
 
 
+def test_multires_merged_level_updates():
+    """A multires level with at most the merge limit of blocks runs each of
+    its updates as one launch over all its blocks (2^(L-1-l) updates of
+    level l per coarse step); limit 0 gives one launch per non-empty group;
+    a negative limit is rejected."""
+    n, levels = 64, 3
+    lm = workloads.multires_cavity(n)
+    faces = {f: (lbm.BC_BOUNCE_BACK, (0, 0, 0)) for f in range(6)}
+    faces[lbm.ZMAX] = (lbm.BC_MOVING_WALL, (0.1, 0.0, 0.0))
+    g = lbm.Grid(n, n, n, kind=lbm.MULTIRES, levels=levels, level_map=lm, periodic=(False,) * 3,
+                 faces=faces, device="cpu")
+    groups = [g.index_map(lbm.MAP_GROUPS, level=l) for l in range(levels)]
+    totals = [int(x[4]) for x in groups]
+    assert max(totals) <= 8192
+    merged = g.launches()
+    assert sorted(merged) == sorted(t for l, t in enumerate(totals) for _ in range(2 ** (levels - 1 - l)))
+    g.set_merge_limit(0)
+    separate = g.launches()
+    per_level = [[int(c) for c in x[:4] if c > 0] for x in groups]
+    assert sorted(separate) == sorted(c for l, cs in enumerate(per_level) for _ in range(2 ** (levels - 1 - l))
+                                      for c in cs)
+    assert len(merged) < len(separate)
+    with pytest.raises(lbm.LbmError):
+        g.set_merge_limit(-1)
+    g.close()
+
+
 @pytest.mark.parametrize("case", [0, 1, 4])
 @pytest.mark.parametrize("grouped", [True, False])
 def test_index_maps_d3q27(orc, case, grouped):

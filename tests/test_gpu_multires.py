@@ -56,7 +56,7 @@ def random_fields(og, seed):
 
 
 def run_pair(orc, n, levels, lm, fluid, periodic, faces, tau, steps, rho, u, storage=lbm.F32,
-             schedule=lbm.DISAGG, collision=0, oracle=True):
+             schedule=lbm.DISAGG, collision=0, oracle=True, merge_limit=None):
     okind = {lbm.BC_BOUNCE_BACK: orc.BB, lbm.BC_MOVING_WALL: orc.MOVING,
              lbm.BC_REG_VELOCITY: orc.REG_VEL, lbm.BC_REG_PRESSURE: orc.REG_PRES}
     bc = [(orc.BB, (0, 0, 0))] * 6
@@ -74,6 +74,8 @@ def run_pair(orc, n, levels, lm, fluid, periodic, faces, tau, steps, rho, u, sto
     for l in range(levels):
         a = og.active(l)
         g.init_equilibrium(rho[l][a], u[l][a].T.copy(), level=l)
+    if merge_limit is not None:
+        g.set_merge_limit(merge_limit)
     g.step(steps)
     out = []
     for l in range(levels):
@@ -101,18 +103,23 @@ def test_multires_periodic_vs_oracle(orc, levels, n, storage, bar):
 
 @pytest.mark.parametrize("collision", [0, 1])
 def test_multires_fused_equals_unfused_bitwise(orc, collision):
+    """Fused and unfused schedules, each with merged level updates (the
+    default for small levels) and with one launch per group, agree bit for
+    bit."""
     n, levels = (64, 32, 32), 3
     lm = blob_level_map(n, levels, (32, 16, 16), 6.0)
     og = orc.MultiresGrid(*n, levels=levels, level_map=lm, tau_coarsest=0.56)
     rho, u = random_fields(og, 5)
     pops = []
     for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG):
-        _, g, _, _ = run_pair(orc, n, levels, lm, None, (True,) * 3, {}, 0.56, 6, rho, u, schedule=sch,
-                              collision=collision, oracle=False)
-        pops.append([g.populations(level=l).cpu().numpy() for l in range(levels)])
-        g.close()
-    for l in range(levels):
-        assert np.array_equal(pops[0][l], pops[1][l]), l
+        for limit in (None, 0):
+            _, g, _, _ = run_pair(orc, n, levels, lm, None, (True,) * 3, {}, 0.56, 6, rho, u, schedule=sch,
+                                  collision=collision, oracle=False, merge_limit=limit)
+            pops.append([g.populations(level=l).cpu().numpy() for l in range(levels)])
+            g.close()
+    for k in range(1, len(pops)):
+        for l in range(levels):
+            assert np.array_equal(pops[0][l], pops[k][l]), (k, l)
 
 
 def test_multires_mass_conserved_on_gpu(orc):
@@ -146,9 +153,10 @@ def test_multires_sphere_tunnel_vs_oracle(orc):
         uu[..., 0] = 0.05
         u.append(uu)
     pops = []
-    for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG):
+    for sch, limit in ((lbm.PLAIN_SINGLE_KERNEL, None), (lbm.DISAGG, None), (lbm.PLAIN_SINGLE_KERNEL, 0),
+                       (lbm.DISAGG, 0)):
         og, g, out, ref = run_pair(orc, n, levels, lm, fluid, (False, True, True), faces, 0.52, 20, rho, u,
-                                   schedule=sch, oracle=(sch == lbm.DISAGG))
+                                   schedule=sch, oracle=(sch == lbm.DISAGG and limit is None), merge_limit=limit)
         pops.append([g.populations(level=l).cpu().numpy() for l in range(levels)])
         if ref is not None:
             for l in range(levels):
@@ -157,8 +165,9 @@ def test_multires_sphere_tunnel_vs_oracle(orc):
                 _say(f"  sphere level {l}: rel L2 u = {err:.3e}")
                 assert err < 1e-5
         g.close()
-    for l in range(levels):
-        assert np.array_equal(pops[0][l], pops[1][l]), l
+    for k in range(1, len(pops)):
+        for l in range(levels):
+            assert np.array_equal(pops[0][l], pops[k][l]), (k, l)
 
 
 def test_multires_lid_driven_cavity_vs_oracle(orc):
@@ -173,9 +182,10 @@ def test_multires_lid_driven_cavity_vs_oracle(orc):
     rho = [np.ones(og.shape(l)) for l in range(levels)]
     u = [np.zeros(og.shape(l) + (3,)) for l in range(levels)]
     pops = []
-    for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG):
+    for sch, limit in ((lbm.PLAIN_SINGLE_KERNEL, None), (lbm.DISAGG, None), (lbm.PLAIN_SINGLE_KERNEL, 0),
+                       (lbm.DISAGG, 0)):
         og, g, out, ref = run_pair(orc, n, levels, lm, None, (False,) * 3, faces, 0.52, 30, rho, u,
-                                   schedule=sch, oracle=(sch == lbm.DISAGG))
+                                   schedule=sch, oracle=(sch == lbm.DISAGG and limit is None), merge_limit=limit)
         pops.append([g.populations(level=l).cpu().numpy() for l in range(levels)])
         if ref is not None:
             for l in range(levels):
@@ -188,5 +198,6 @@ def test_multires_lid_driven_cavity_vs_oracle(orc):
             _say(f"  mass drift {abs(m1 - m0) / m0:.2e}")
             assert abs(m1 - m0) / m0 < 1e-6
         g.close()
-    for l in range(levels):
-        assert np.array_equal(pops[0][l], pops[1][l]), l
+    for k in range(1, len(pops)):
+        for l in range(levels):
+            assert np.array_equal(pops[0][l], pops[k][l]), (k, l)
