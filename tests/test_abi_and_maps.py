@@ -90,6 +90,31 @@ def test_error_paths():
         lbm.lbm_grid_create(d)
 
 
+def test_size_limits_and_empty_grids():
+    """Block coordinates are packed in 10 bits per axis: 4092 voxels per axis
+    is the largest block grid, 4096 is rejected.  A block-sparse grid with no
+    fluid voxel and a box with a zero extent are rejected; the dense
+    lexicographic arm takes any box size (partial tiles)."""
+    g = lbm.lbm_grid_create(_desc(n=(4092, 4, 4)))
+    lbm.lbm_grid_commit(g)
+    lbm.lbm_grid_destroy(g)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_grid_commit(lbm.lbm_grid_create(_desc(n=(4096, 4, 4))))
+    assert "4092" in str(e.value)
+    d = _desc(kind=lbm.BLOCK_SPARSE)
+    empty = np.zeros((8, 8, 8), np.uint8)
+    d.fluid_mask = empty.ctypes.data
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_grid_commit(lbm.lbm_grid_create(d))
+    assert "no fluid voxel" in str(e.value)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_grid_commit(lbm.lbm_grid_create(_desc(n=(0, 8, 8), schedule=lbm.PLAIN_SINGLE_KERNEL)))
+    for n in ((10, 8, 8), (1, 16, 1), (3, 3, 3)):
+        g = lbm.lbm_grid_create(_desc(n=n, schedule=lbm.PLAIN_SINGLE_KERNEL))
+        lbm.lbm_grid_commit(g)
+        lbm.lbm_grid_destroy(g)
+
+
 CASES = [
     # (n, periodic, face kinds for XMIN..ZMAX, dense)
     ((16, 12, 8), (False, True, True), ("vel", "pres", "bb", "bb", "bb", "bb"), False),
