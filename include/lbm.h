@@ -181,6 +181,13 @@ lbm_status lbm_read_macroscopic(lbm_grid *g, int32_t level, void *rho_dev, void 
  * (fixed-order two-pass sum). */
 lbm_status lbm_reduce(lbm_grid *g, double *out5_dev, void *stream);
 
+/* Health check: runs the reductions above into the grid's workspace, waits
+ * for the stream and returns LBM_ERR_NUMERIC if any sum is not finite.  A
+ * NaN or infinite population anywhere makes the mass sum non-finite, so
+ * this detects every blown-up state (the kernels themselves never test for
+ * it).  Synchronizes `stream`; off the timed loop. */
+lbm_status lbm_check(lbm_grid *g, void *stream);
+
 /* Post-collision populations of `level` as FP64 [q][N] in canonical order. */
 lbm_status lbm_read_populations(lbm_grid *g, int32_t level, double *f_dev, void *stream);
 /* Overwrites the populations of `level` from FP64 [q][N] canonical order

@@ -108,7 +108,7 @@ struct lbm_grid {
   BlockLevel single;              // dense / block-sparse
   std::vector<MultiresLevel> mr;  // multires
   std::vector<LevelRT> lv;
-  size_t off_partial = 0, total = 0;
+  size_t off_partial = 0, off_check = 0, total = 0;
   int64_t partial_rows = 0;
   char *ws = nullptr;
 };
@@ -479,6 +479,8 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
   }
   g->off_partial = off;
   off = align256(off + (size_t)g->partial_rows * 5 * sizeof(double));
+  g->off_check = off;  // five doubles for lbm_check
+  off = align256(off + 5 * sizeof(double));
   g->total = off;
   *bytes = g->total;
   g->state = kCommitted;
@@ -636,6 +638,22 @@ lbm_status lbm_reduce(lbm_grid *g, double *out5, void *stream) {
   }
   if (e == hipSuccess) e = g->ops.reduce_final(partial, g->partial_rows, out5, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "reduce");
+  return LBM_OK;
+}
+
+lbm_status lbm_check(lbm_grid *g, void *stream) {
+  if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
+  if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
+  double *d = (double *)(g->ws + g->off_check);
+  if (lbm_status st = lbm_reduce(g, d, stream)) return st;
+  double h[5];
+  hipError_t e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "check");
+  for (int k = 0; k < 5; ++k)
+    if (!std::isfinite(h[k]))
+      return fail(LBM_ERR_NUMERIC, "non-finite populations (mass %g, momentum %g %g %g, energy %g)", h[0], h[1],
+                  h[2], h[3], h[4]);
   return LBM_OK;
 }
 

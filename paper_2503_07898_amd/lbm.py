@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
             "lbm_mlp_destroy": ([vp], i32),
             "lbm_set_collision": ([vp, i32, vp], i32),
             "lbm_set_merge_limit": ([vp, i64], i32),
+            "lbm_check": ([vp, vp], i32),
             "lbm_sample_populations": ([vp, i32, ctypes.c_uint64, i64, vp, vp], i32),
             "lbm_grid_destroy": ([vp], i32),
         }
@@ -268,6 +269,10 @@ def lbm_set_collision(g, collision: int, mlp=None) -> None:
     check(lib().lbm_set_collision(g, int(collision), mlp))
 
 
+def lbm_check(g, stream=None) -> None:
+    check(lib().lbm_check(g, _stream_ptr(stream)))
+
+
 def lbm_set_merge_limit(g, max_blocks: int) -> None:
     check(lib().lbm_set_merge_limit(g, int(max_blocks)))
 
@@ -395,6 +400,10 @@ class Grid:
     def set_collision(self, collision: int, mlp=None) -> None:
         self._mlp_keep = mlp
         lbm_set_collision(self.h, collision, None if mlp is None else mlp.h)
+
+    def check(self) -> None:
+        """Raises LbmError (status LBM_ERR_NUMERIC) if any population is NaN or infinite."""
+        lbm_check(self.h)
 
     def set_merge_limit(self, max_blocks: int) -> None:
         lbm_set_merge_limit(self.h, max_blocks)

@@ -70,6 +70,9 @@ def test_error_paths():
         lbm.lbm_set_boundary(g, lbm.XMIN, lbm.BC_BOUNCE_BACK)  # after commit
     assert e.value.status == -4
     with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_check(g, stream=0)  # no populations yet
+    assert e.value.status == -4
+    with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_grid_bind(g, 0x1000 + 7, 1 << 30, stream=0)  # misaligned workspace
     assert "aligned" in str(e.value)
     lbm.lbm_grid_destroy(g)

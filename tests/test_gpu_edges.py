@@ -175,3 +175,25 @@ def test_isolated_fluid_voxels(orc):
         pops.append(g.populations().cpu().numpy())
         g.close()
     assert np.array_equal(pops[0], pops[1]) and np.array_equal(pops[0], pops[2])
+
+
+@pytest.mark.parametrize("storage", [lbm.F32, lbm.F16_SHIFTED])
+def test_check_reports_non_finite_populations(storage):
+    """lbm_check passes on a healthy field and returns LBM_ERR_NUMERIC once
+    one population is NaN (written through lbm_write_populations), and the
+    NaN spreads through the steps without any kernel fault."""
+    n = (16, 16, 16)
+    g = lbm.Grid(*n, kind=lbm.DENSE, tau=0.6, storage=storage).bind()
+    g.init_equilibrium(np.ones(16 ** 3), np.zeros((3, 16 ** 3)))
+    g.step(5)
+    g.check()
+    f = g.populations()
+    f[7, 1234] = float("nan")
+    g.write_populations(f)
+    with pytest.raises(lbm.LbmError) as e:
+        g.check()
+    assert e.value.status == -6
+    g.step(3)
+    with pytest.raises(lbm.LbmError):
+        g.check()
+    g.close()
