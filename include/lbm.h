@@ -17,9 +17,9 @@
  *   - multi-resolution grids ("Disaggregation on a Multi-resolution
  *     Domain"): per level, blocks near a resolution jump and uniform blocks,
  *     with collide and stream fused on the uniform ones.
- * The update itself is the LBM of the evaluation section: D3Q19, BGK
- * collision, halfway bounce-back on obstacles, regularized inflow/outflow
- * faces, and a moving-wall lid for the lid-driven cavity.
+ * The update itself is the LBM of the evaluation section: D3Q19 (D3Q27 on
+ * request), BGK collision, halfway bounce-back on obstacles, regularized
+ * inflow/outflow faces, and a moving-wall lid for the lid-driven cavity.
  *
  * Conventions shared by every call
  *   - Every function returns an lbm_status and never aborts.  On failure,
@@ -225,7 +225,9 @@ lbm_status lbm_get_index_map(const lbm_grid *g, int32_t level, lbm_map which, vo
                              size_t *count);
 
 /* Kernel launches one lbm_step issues per (coarse) time step, and the blocks
- * each of them covers (for checking the structure of table dissBlock).
+ * each of them covers (for checking the structure of table dissBlock; a
+ * merged multires level update, see lbm_set_merge_limit, covers all blocks
+ * of its level).
  * blocks_out[max] receives block counts per launch; *n receives the launch
  * count. */
 lbm_status lbm_step_launches(const lbm_grid *g, int64_t *blocks_out, int32_t max, int32_t *n);
@@ -236,7 +238,9 @@ lbm_status lbm_step_launches(const lbm_grid *g, int64_t *blocks_out, int32_t max
  * standardized non-equilibrium part per unit density of a voxel,
  * g = (f - f^eq(rho, u))/rho; output: an
  * estimate y of the regularized operator's non-equilibrium part per unit
- * density, projected to zero mass and momentum, P(y); post-collision state
+ * density, projected onto the second-order Hermite space (no mass, momentum
+ * or higher-order content: P(y)_i = w_i/(2 c_s^4) Q_i : sum_j Q_j y_j with
+ * Q_i = c_i c_i - c_s^2 I); post-collision state
  * f* = f^eq + (1 - 1/tau) rho P(y).  Inference and training forward run on
  * the matrix cores in bfloat16 with FP32 accumulation; FP32 master weights
  * are trained with Adam (beta 0.9 / 0.999, eps 1e-8) on the mean squared
