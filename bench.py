@@ -173,8 +173,8 @@ def main(argv=None) -> int:
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(one process drives one GPU); use --gpus 1", file=sys.stderr)
         return 2
 
     import torch

@@ -60,7 +60,7 @@ typedef enum {
   LBM_ERR_OUT_OF_MEMORY = -2, /* host allocation failed */
   LBM_ERR_HIP = -3,           /* a HIP runtime call failed; message holds hipGetErrorString */
   LBM_ERR_STATE = -4,         /* call out of order */
-  LBM_ERR_UNSUPPORTED = -5,   /* valid request this build does not implement */
+  LBM_ERR_UNSUPPORTED = -5,   /* valid request the library does not implement */
   LBM_ERR_NUMERIC = -6        /* non-finite values found by lbm_check */
 } lbm_status;
 

@@ -16,7 +16,7 @@
  *    surfaces and regularized inflow/outflow faces (Latt et al. 2008).
  *  - "Improving LBM scalability", benchmarking paragraph: lid-driven cavity,
  *    read as bounce-back walls plus a moving-wall bounce-back lid.
- *  - Regularized collision operator (an addition of this build; the same
+ *  - Regularized collision operator (an addition of this library; the same
  *    Hermite projection the regularized boundary uses).
  *
  * State convention: the stored field is the post-collision population f* of

@@ -3,7 +3,7 @@
 Only tests/, the smoke check and bench.py's CPU-baseline leg use this
 module; it shares no code with the GPU library.
 
-The closure (an addition of this build; nothing in the paper): a
+The closure (an addition of this library; nothing in the paper): a
 19 -> 64 -> 64 -> 19 perceptron with tanh-form GELU activations maps the
 standardized non-equilibrium part of a voxel per unit density,
 g = (f - f^eq(rho, u)) / rho, to an estimate y of the regularized
