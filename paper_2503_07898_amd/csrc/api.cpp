@@ -78,7 +78,7 @@ struct LatticeLaunchers {
   hipError_t (*read_pop)(const SlotArgs &, double *, hipStream_t);
   hipError_t (*write_pop)(const SlotArgs &, const double *, hipStream_t);
   hipError_t (*reduce_partial)(const SlotArgs &, double, double *, hipStream_t);
-  hipError_t (*reduce_final)(const double *, int64_t, double *, hipStream_t);
+  hipError_t (*reduce_final)(const double *, int64_t, double *, double *, hipStream_t);
 };
 #define LBM_LAUNCHERS_OF(ns)                                                                          \
   LatticeLaunchers {                                                                                  \
@@ -108,7 +108,7 @@ struct lbm_grid {
   BlockLevel single;              // dense / block-sparse
   std::vector<MultiresLevel> mr;  // multires
   std::vector<LevelRT> lv;
-  size_t off_partial = 0, off_check = 0, total = 0;
+  size_t off_partial = 0, off_mid = 0, off_check = 0, total = 0;
   int64_t partial_rows = 0;
   char *ws = nullptr;
 };
@@ -479,6 +479,8 @@ lbm_status lbm_grid_commit(lbm_grid *g, size_t *bytes) {
   }
   g->off_partial = off;
   off = align256(off + (size_t)g->partial_rows * 5 * sizeof(double));
+  g->off_mid = off;  // chunk sums of the second reduction pass
+  off = align256(off + (size_t)reduce_mid_rows(g->partial_rows) * 5 * sizeof(double));
   g->off_check = off;  // five doubles for lbm_check
   off = align256(off + 5 * sizeof(double));
   g->total = off;
@@ -636,7 +638,8 @@ lbm_status lbm_reduce(lbm_grid *g, double *out5, void *stream) {
     e = g->ops.reduce_partial(slot_args(g, r), (double)(1ll << (3 * l)), partial + r.partial_row0 * 5,
                               (hipStream_t)stream);
   }
-  if (e == hipSuccess) e = g->ops.reduce_final(partial, g->partial_rows, out5, (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = g->ops.reduce_final(partial, g->partial_rows, (double *)(g->ws + g->off_mid), out5, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "reduce");
   return LBM_OK;
 }

@@ -101,6 +101,11 @@ hipError_t launch_sample_pre(const StepArgs &a, int32_t storage, int32_t b0, int
                              float *out, hipStream_t s);
 }  // namespace k19
 
+// FP64 reductions run in three fixed-order passes: one partial row per 64
+// slots, sums of kReduceChunk rows, then one sum of those.
+constexpr int64_t kReduceChunk = 2048;
+inline int64_t reduce_mid_rows(int64_t rows) { return rows > 0 ? (rows + kReduceChunk - 1) / kReduceChunk : 1; }
+
 // Utility kernels over a slot range [0, nslots) with an optional canonical
 // map (NULL = identity, every slot fluid).
 struct SlotArgs {
@@ -125,7 +130,7 @@ struct SlotArgs {
   hipError_t launch_write_populations(const SlotArgs &A, const double *f, hipStream_t s);               \
   /* partial sums per 64-slot group (weighted by `weight`) into partial[first_row..] */                 \
   hipError_t launch_reduce_partial(const SlotArgs &A, double weight, double *partial, hipStream_t s);   \
-  hipError_t launch_reduce_final(const double *partial, int64_t rows, double *out5, hipStream_t s);
+  hipError_t launch_reduce_final(const double *partial, int64_t rows, double *mid, double *out5, hipStream_t s);
 
 namespace k19 {
 LBM_DECLARE_LATTICE_LAUNCHERS

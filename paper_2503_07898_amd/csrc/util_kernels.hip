@@ -103,10 +103,11 @@ __global__ void k_write_pop(SlotArgs A, const double *f) {
 // Per 64-slot row partial sums: mass, momentum, kinetic energy, times weight.
 // One wave per row, butterfly reduction in a fixed order.
 template <class ST>
-__global__ __launch_bounds__(64) void k_reduce_partial(SlotArgs A, double weight, double *partial) {
+__global__ __launch_bounds__(256) void k_reduce_partial(SlotArgs A, double weight, double *partial) {
   using T = typename ST::T;
-  const int64_t row = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // one row of 64 slots per wave
+  if (row * 64 >= A.nslots) return;
+  const int lane = threadIdx.x & 63;
   const int64_t slot = row * 64 + lane;
   double v[5] = {0, 0, 0, 0, 0};
   if (slot < A.nslots && canon_of(A, slot) >= 0) {
@@ -135,12 +136,15 @@ __global__ __launch_bounds__(64) void k_reduce_partial(SlotArgs A, double weight
     for (int k = 0; k < 5; ++k) partial[row * 5 + k] = weight * v[k];
 }
 
-__global__ __launch_bounds__(256) void k_reduce_final(const double *partial, int64_t rows, double *out5) {
+// Fixed-order sum of rows [r0, r1) of a [rows][5] array by one 256-thread
+// workgroup: thread t adds rows r0 + t, r0 + t + 256, ... in turn, then a
+// fixed LDS tree; the result does not depend on timing.
+__device__ __forceinline__ void sum_rows(const double *in, int64_t r0, int64_t r1, double *out5) {
   __shared__ double sh[5][256];
   const int t = threadIdx.x;
   double acc[5] = {0, 0, 0, 0, 0};
-  for (int64_t r = t; r < rows; r += 256)
-    for (int k = 0; k < 5; ++k) acc[k] += partial[r * 5 + k];
+  for (int64_t r = r0 + t; r < r1; r += 256)
+    for (int k = 0; k < 5; ++k) acc[k] += in[r * 5 + k];
   for (int k = 0; k < 5; ++k) sh[k][t] = acc[k];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -149,6 +153,18 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double *partial, int
     __syncthreads();
   }
   if (t < 5) out5[t] = sh[t][0];
+}
+
+// Second pass: chunks of kReduceChunk partial rows, one workgroup each.
+__global__ __launch_bounds__(256) void k_reduce_mid(const double *partial, int64_t rows, double *mid) {
+  const int64_t r0 = (int64_t)blockIdx.x * kReduceChunk;
+  const int64_t r1 = r0 + kReduceChunk < rows ? r0 + kReduceChunk : rows;
+  sum_rows(partial, r0, r1, mid + (int64_t)blockIdx.x * 5);
+}
+
+// Third pass: the chunk sums, one workgroup.
+__global__ __launch_bounds__(256) void k_reduce_final(const double *mid, int64_t nmid, double *out5) {
+  sum_rows(mid, 0, nmid, out5);
 }
 
 template <template <class> class K, class... Args>
@@ -189,10 +205,14 @@ hipError_t launch_write_populations(const SlotArgs &A, const double *f, hipStrea
 hipError_t launch_reduce_partial(const SlotArgs &A, double weight, double *partial, hipStream_t s) {
   const int64_t rows = (A.nslots + 63) / 64;
   if (rows == 0) return hipSuccess;
-  return dispatch<RedK>(A.storage, dim3((unsigned)rows), dim3(64), s, A, weight, partial);
+  return dispatch<RedK>(A.storage, dim3((unsigned)((rows + 3) / 4)), dim3(256), s, A, weight, partial);
 }
-hipError_t launch_reduce_final(const double *partial, int64_t rows, double *out5, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partial, rows, out5);
+hipError_t launch_reduce_final(const double *partial, int64_t rows, double *mid, double *out5, hipStream_t s) {
+  const int64_t nmid = reduce_mid_rows(rows);
+  hipLaunchKernelGGL(k_reduce_mid, dim3((unsigned)nmid), dim3(256), 0, s, partial, rows, mid);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, mid, nmid, out5);
   return hipGetLastError();
 }
 
