@@ -63,18 +63,19 @@ __global__ void k_read_macro(SlotArgs A, void *rho_out, void *u_out, int f64) {
     jz += kCz[i] * h;
   }
   const double r = 1.0 + d;
+  const double ir = 1.0 / r;  // one FP64 division per voxel
   if (f64) {
     double *ro = (double *)rho_out, *uo = (double *)u_out;
     ro[c] = r;
-    uo[c] = jx / r;
-    uo[A.n + c] = jy / r;
-    uo[2 * A.n + c] = jz / r;
+    uo[c] = jx * ir;
+    uo[A.n + c] = jy * ir;
+    uo[2 * A.n + c] = jz * ir;
   } else {
     float *ro = (float *)rho_out, *uo = (float *)u_out;
     ro[c] = (float)r;
-    uo[c] = (float)(jx / r);
-    uo[A.n + c] = (float)(jy / r);
-    uo[2 * A.n + c] = (float)(jz / r);
+    uo[c] = (float)(jx * ir);
+    uo[A.n + c] = (float)(jy * ir);
+    uo[2 * A.n + c] = (float)(jz * ir);
   }
 }
 
