@@ -52,10 +52,15 @@ LBM_HD constexpr float weight_f(int i) {
 
 #ifdef LBM_Q27
 #define LBM_LATTICE_NS k27
+// reopen either lattice's namespace with the inline-ness it has in this build
+#define LBM_NAMESPACE_K19 namespace k19
+#define LBM_NAMESPACE_K27 inline namespace k27
 inline namespace k27 {
 using namespace d3q27;
 #else
 #define LBM_LATTICE_NS k19
+#define LBM_NAMESPACE_K19 inline namespace k19
+#define LBM_NAMESPACE_K27 namespace k27
 inline namespace k19 {
 using namespace d3q19;
 #endif

@@ -90,7 +90,7 @@ struct MlpBuffers {
   int64_t batch_max;
 };
 
-namespace k19 {  // D3Q19 only
+LBM_NAMESPACE_K19 {  // D3Q19 only
 hipError_t mlp_pack(const MlpBuffers &B, hipStream_t s);
 hipError_t mlp_fit_standardization(const MlpBuffers &B, const float *f, int64_t n, hipStream_t s);
 hipError_t mlp_forward(const MlpBuffers &B, const float *f, int64_t n, float *y, hipStream_t s);
@@ -132,10 +132,10 @@ struct SlotArgs {
   hipError_t launch_reduce_partial(const SlotArgs &A, double weight, double *partial, hipStream_t s);   \
   hipError_t launch_reduce_final(const double *partial, int64_t rows, double *mid, double *out5, hipStream_t s);
 
-namespace k19 {
+LBM_NAMESPACE_K19 {
 LBM_DECLARE_LATTICE_LAUNCHERS
 }
-namespace k27 {
+LBM_NAMESPACE_K27 {
 LBM_DECLARE_LATTICE_LAUNCHERS
 }
 
