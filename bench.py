@@ -20,7 +20,7 @@ sphere and the multires lid-driven cavity (unfused baseline against fused),
 the regularized operator and the learned closure (with the share of HBM and
 matrix-core peak of its interior launch).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--arms all|none]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--arms all|none|closure|storage]
 """
 from __future__ import annotations
 
@@ -165,8 +165,9 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--arms", default="all", choices=["all", "none", "closure"],
-                    help="closure: only the learned-closure arms (for counter runs)")
+    ap.add_argument("--arms", default="all", choices=["all", "none", "closure", "storage"],
+                    help="closure: only the learned-closure arms; storage: only the 16-bit cavity "
+                         "arms (both for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (torch) 5 times, the reference "
@@ -230,7 +231,7 @@ def main(argv=None) -> int:
     torch.cuda.empty_cache()
 
     arms = {}
-    if args.arms in ("all", "closure"):
+    if args.arms in ("all", "closure", "storage"):
         def arm(name, make, steps, bytes_per_update, interior=False):
             log(name)
             gg = make()
@@ -254,6 +255,9 @@ def main(argv=None) -> int:
             gg.close()
             torch.cuda.empty_cache()
 
+    if args.arms == "storage":
+        arm("cavity256_f16_disagg", lambda: cases.cavity(storage=lbm.F16_SHIFTED), 20, 76)
+        arm("cavity256_bf16_disagg", lambda: cases.cavity(storage=lbm.BF16_SHIFTED), 20, 76)
     if args.arms == "all":
         arm("cavity256_f32_plain_lexicographic", lambda: cases.cavity(schedule=lbm.PLAIN_SINGLE_KERNEL), 100, 152)
         arm("cavity256_f16_disagg", lambda: cases.cavity(storage=lbm.F16_SHIFTED), 100, 76)
