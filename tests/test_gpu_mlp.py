@@ -103,7 +103,7 @@ def test_closure_step_matches_oracle(orc, mlpo):
     m = lbm.Mlp()
     m.set_params(lbm.flatten_params(workloads.mlp_he_uniform(9)))
     m.fit_standardization(data)
-    for storage, judge in ((lbm.F32, 0.0), (lbm.F16_SHIFTED, 0.0), (lbm.F32, 0.01)):
+    for storage, judge in ((lbm.F32, 0.0), (lbm.F16_SHIFTED, 0.0), (lbm.BF16_SHIFTED, 0.0), (lbm.F32, 0.01)):
         m.set_judge(judge)
         g = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau, storage=storage).bind()
         g.set_collision(lbm.MLP, m)
@@ -125,7 +125,10 @@ def test_closure_step_matches_oracle(orc, mlpo):
         e = rel(f1 - feq, ref - feq)
         _say(f"  storage {storage} judge {judge}: rel L2 of f* - f^eq vs oracle closure {e:.2e}, "
              f"fallbacks gpu {fb} oracle {int(fell.sum())}")
-        assert e < 1e-2
+        # the compared part f* - f^eq is small next to the stored h = f* - w,
+        # so bfloat16's rounding of h (8 significant bits against binary16's
+        # 11) shows in it 8x more; its bar is the 2e-2 of the other bfloat16 tests
+        assert e < (2e-2 if storage == lbm.BF16_SHIFTED else 1e-2)
         # decisions taken in different precisions may differ at the threshold
         assert abs(fb - int(fell.sum())) <= max(2, fell.size // 200)
     m.close()
