@@ -241,6 +241,13 @@ def main(argv=None) -> int:
             arms[name] = {"MLUPS": round(m, 1),
                           "hbm_frac_alg": round(m * 1e6 * bytes_per_update / 1e9 / HBM_PEAK_GBS, 4),
                           "fluid_voxels": n_up, "launch_blocks": gg.launches()}
+            if getattr(gg, "kind", None) == lbm.BLOCK_SPARSE:
+                # per-slot reading: every slot of an active block moves its bytes,
+                # solid or fluid
+                slots = int(gg.index_map(lbm.MAP_GROUPS)[4]) * 64
+                arms[name]["slots"] = slots
+                arms[name]["hbm_frac_slot"] = round(m * 1e6 * slots / n_up * bytes_per_update / 1e9
+                                                    / HBM_PEAK_GBS, 4)
             if interior:
                 # the interior (full-group) launch alone: HBM and matrix-core shares
                 _, _, _, nf, _ = gg.index_map(lbm.MAP_GROUPS)
