@@ -154,8 +154,17 @@ def cpu_baseline(workloads, budget_s: float = 15.0):
     g.run(f, 1)
     dt1 = time.perf_counter() - t0
     omp_set(threads)
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(n ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle", "value_1_thread": round(n ** 3 / dt1 / 1e6, 3),
+            "kind": "oracle", "value_1_thread": round(n ** 3 / dt1 / 1e6, 3), "cpu": cpu,
             "sample": f"FP64 oracle, dense lid-driven cavity 256^3 (full box), {steps} step(s) in "
                       f"{dt:.1f} s on {threads} OpenMP threads; 1 step in {dt1:.1f} s on 1 thread"}
 
