@@ -18,8 +18,8 @@ struct FaceParams {
 };
 
 struct StepArgs {
-  const void *src;           // [19][S] populations read (post-collision of the last step)
-  void *dst;                 // [19][S] populations written
+  const void *src;           // populations read (post-collision of the last step), S slots
+  void *dst;                 // populations written; block layouts index both with pidx
   uint32_t S;                // plane stride in slots
   const int32_t *nbr;        // [nblocks][Q-1] neighbour block slots (-1 = none)
   const uint64_t *bbm;       // [nblocks][Q-1] bounce masks

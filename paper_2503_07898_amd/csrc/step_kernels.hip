@@ -1,11 +1,12 @@
 // Fused pull collide-and-stream kernels of liblbm (gfx950).
 //
 // Block layouts: one wave64 per 4^3-voxel block, lane = voxel x+4y+16z,
-// four blocks per 256-thread workgroup.  Populations are structure-of-arrays
-// [19][S] with S = 64 * blocks, so every population load of a wave is one
-// 256-byte (FP32) or 128-byte (16-bit) row of its own block plus the face and
-// edge rows of the neighbour blocks it pulls across.  Neighbour block slots
-// and bounce masks are wave-uniform and come through scalar loads.
+// four blocks per 256-thread workgroup.  Populations are block-interleaved
+// (pidx): each block's Q rows of 64 values are contiguous, so every
+// population load of a wave is one 256-byte (FP32) or 128-byte (16-bit) row
+// of its own block plus the face and edge rows of the neighbour blocks it
+// pulls across.  Neighbour block slots and bounce masks are wave-uniform and
+// come through scalar loads.
 //
 // Kernels per group (the disaggregated design's group-specific operations):
 //   full      -- every pulled source is a fluid voxel; no masks, no checks;
