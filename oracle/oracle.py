@@ -312,14 +312,18 @@ def _face_voxel_kinds(nx, ny, nz, periodic, face_kinds, heavy):
 
 
 def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, grouped: bool = True,
-                     q: int = 19):
+                     q: int = 19, jump=None):
     """Returns a dict with coords [nb,3], nbr [nb,18], fmask [nb] (uint64),
     groups (n_boundary, n_masked, n_full), group [nb] (0 boundary, 1 masked,
-    2 full, per storage slot), canon [nb*64] (int64, -1 = not fluid),
-    n_fluid.  grouped: memory-based grouping (boundary, masked, full groups
-    stored one after the other, Morton order inside each); otherwise the
-    bitmask-based form keeps every block in one Morton order.  q: lattice
-    (19: 18 face/edge neighbours; 27: 26 with the corners)."""
+    2 full, 3 jump, per storage slot), canon [nb*64] (int64, -1 = not fluid),
+    n_fluid, and groups4 (n_jump, n_boundary, n_masked, n_full).  grouped:
+    memory-based grouping (jump, boundary, masked, full groups stored one
+    after the other, Morton order inside each); otherwise the bitmask-based
+    form keeps every block in one Morton order.  q: lattice (19: 18
+    face/edge neighbours; 27: 26 with the corners).  jump: optional bool
+    (nz,ny,nx) of voxels at distance 0 from a resolution jump (multires
+    levels); a block holding one belongs to the jump group, whatever else
+    it holds."""
     c, _, _ = lattice(q)
     B = 4
     assert nx % B == 0 and ny % B == 0 and nz % B == 0
@@ -347,7 +351,11 @@ def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, group
                 t[a] %= nb[a]
         return tuple(t) if tuple(t) in active else None
 
+    jm = None if jump is None else np.asarray(jump, bool)
+
     def group_of(bx, by, bz):
+        if jm is not None and block_view(jm, bx, by, bz).any():
+            return 3
         if dense:
             shell = ((not periodic[0] and (bx == 0 or bx == nbx - 1)) or
                      (not periodic[1] and (by == 0 or by == nby - 1)) or
@@ -364,16 +372,16 @@ def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, group
                 full = False
         return 2 if full else 1
 
-    groups = {0: [], 1: [], 2: []}
+    groups = {3: [], 0: [], 1: [], 2: []}
     for key in active:
         groups[group_of(*key)].append(key)
     order = []
     if grouped:
-        for gid in (0, 1, 2):
+        for gid in (3, 0, 1, 2):
             order += sorted(groups[gid], key=lambda k: morton_key(*k))
     else:
         order = sorted(active, key=lambda k: morton_key(*k))
-    gid_of = {k: gid for gid in (0, 1, 2) for k in groups[gid]}
+    gid_of = {k: gid for gid in (3, 0, 1, 2) for k in groups[gid]}
     slot_of = {k: s for s, k in enumerate(order)}
     nb = len(order)
     coords = np.array(order, np.int32).reshape(nb, 3)
@@ -404,8 +412,63 @@ def build_block_maps(nx, ny, nz, periodic, fluid, face_kinds, dense: bool, group
                     canon[s * 64 + lx + 4 * ly + 16 * lz] = v[lz, ly, lx]
     return dict(coords=coords, nbr=nbr, fmask=fmask,
                 groups=tuple(len(groups[g]) for g in (0, 1, 2)),
+                groups4=tuple(len(groups[g]) for g in (3, 0, 1, 2)),
                 group=np.array([gid_of[k] for k in order], np.int32),
                 canon=canon, n_fluid=int(fl.sum()))
+
+
+def multires_level_masks(nx, ny, nz, levels, periodic, level_map, fluid=None):
+    """Active and jump voxels of every level of a multi-resolution box
+    ("Disaggregation on a Multi-resolution Domain": the discrete distance
+    property P_d, distance 0 meaning immediate proximity to a resolution
+    jump).  Readings: a level-l voxel is the cube of 2^l finest cells whose
+    level-map entry is l (solids exist on level 0 only); a level-l voxel is
+    at distance 0 if one of the voxels it pulls from along a D3Q19 link
+    (face or edge neighbour, periodic axes wrapped, sources outside a
+    non-periodic face ignored) belongs to another level's territory.
+    Direct coordinate search; returns [(active, jump)] with bool arrays
+    shaped (nz >> l, ny >> l, nx >> l)."""
+    c, _, _ = lattice()
+    lm = np.asarray(level_map)
+    fl = np.ones((nz, ny, nx), bool) if fluid is None else np.asarray(fluid, bool)
+    out = []
+    for l in range(levels):
+        n = (nx >> l, ny >> l, nz >> l)
+
+        def territory(x, y, z):
+            return int(lm[z << l, y << l, x << l])
+
+        act = np.zeros((n[2], n[1], n[0]), bool)
+        jmp = np.zeros((n[2], n[1], n[0]), bool)
+        for z in range(n[2]):
+            for y in range(n[1]):
+                for x in range(n[0]):
+                    if territory(x, y, z) != l or (l == 0 and not fl[z, y, x]):
+                        continue
+                    act[z, y, x] = True
+                    for i in range(1, 19):
+                        src = [x - int(c[i, 0]), y - int(c[i, 1]), z - int(c[i, 2])]
+                        inside = True
+                        for a in range(3):
+                            if src[a] < 0 or src[a] >= n[a]:
+                                if not periodic[a]:
+                                    inside = False
+                                src[a] %= n[a]
+                        if inside and territory(*src) != l:
+                            jmp[z, y, x] = True
+                            break
+        out.append((act, jmp))
+    return out
+
+
+def build_multires_maps(nx, ny, nz, levels, periodic, level_map, fluid, face_kinds):
+    """Per level, the block maps of build_block_maps on the level's own box
+    (voxel mask = the level's active voxels, jump group from
+    multires_level_masks)."""
+    maps = []
+    for l, (act, jmp) in enumerate(multires_level_masks(nx, ny, nz, levels, periodic, level_map, fluid)):
+        maps.append(build_block_maps(nx >> l, ny >> l, nz >> l, periodic, act, face_kinds, False, jump=jmp))
+    return maps
 
 
 def brute_force_neighbours(coords, periodic, nblocks_axis):

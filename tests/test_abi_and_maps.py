@@ -322,3 +322,49 @@ def test_d3q27_restrictions():
                  q=27, device="cpu")
     with pytest.raises(lbm.LbmError):
         lbm.Grid(8, 8, 8, q=23, device="cpu")
+
+
+MR_CASES = [
+    # (levels, n, periodic, face kinds XMIN..ZMAX, obstacle radius or 0)
+    (2, (32, 32, 32), (True, True, True), ("bb",) * 6, 0.0),
+    (3, (64, 32, 32), (True, True, True), ("bb",) * 6, 0.0),
+    (3, (128, 32, 32), (False, True, True), ("vel", "pres", "bb", "bb", "bb", "bb"), 3.0),
+    (2, (48, 48, 48), (False, False, False), ("bb", "bb", "bb", "bb", "bb", "moving"), 0.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(MR_CASES)))
+@pytest.mark.parametrize("seed", [0, 1])
+def test_multires_index_maps_bit_exact(orc, case, seed):
+    """Every level of a multires grid: groups [jump | boundary | masked |
+    full] (jump = blocks holding a voxel at distance 0 from a resolution
+    jump), block coordinates in Morton order per group, neighbour tables,
+    fluid masks and canonical indices equal to the oracle's coordinate-search
+    builder, bit for bit."""
+    from test_oracle_multires import blob_level_map
+    levels, n, periodic, kinds, obst = MR_CASES[case]
+    rng = np.random.default_rng(seed + 7 * case)
+    centre = (n[0] / 2 + rng.uniform(-3, 3), n[1] / 2 + rng.uniform(-2, 2), n[2] / 2 + rng.uniform(-2, 2))
+    radius = 6.0 if obst else rng.uniform(3.0, 6.0)
+    lm = blob_level_map(n, levels, centre, radius, band=6.0 if obst else 4.0, periodic=periodic)
+    fluid = None
+    if obst:
+        z, y, x = np.meshgrid(*(np.arange(k, dtype=float) for k in (n[2], n[1], n[0])), indexing="ij")
+        fluid = ((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2 > obst ** 2).astype(np.uint8)
+    g = lbm.Grid(*n, kind=lbm.MULTIRES, levels=levels, level_map=lm, fluid=fluid, periodic=periodic,
+                 faces=_faces(periodic, kinds), tau=0.55, device="cpu")
+    okinds = [{"bb": orc.BB, "moving": orc.MOVING, "vel": orc.REG_VEL, "pres": orc.REG_PRES}[k]
+              for k in kinds]
+    ref = orc.build_multires_maps(*n, levels, periodic, lm, fluid, okinds)
+    for l in range(levels):
+        r = ref[l]
+        groups = g.index_map(lbm.MAP_GROUPS, level=l)
+        assert tuple(int(x) for x in groups[:4]) == r["groups4"], l
+        assert r["groups4"][0] > 0  # every level meets a resolution jump
+        nb = int(groups[4])
+        assert np.array_equal(g.index_map(lbm.MAP_COORDS, level=l).reshape(nb, 3), r["coords"])
+        assert np.array_equal(g.index_map(lbm.MAP_NEIGHBOURS, level=l).reshape(nb, 18), r["nbr"])
+        assert np.array_equal(g.index_map(lbm.MAP_FLUIDMASK, level=l), r["fmask"])
+        assert np.array_equal(g.index_map(lbm.MAP_CANONICAL, level=l), r["canon"])
+        assert g.n_level(l) == r["n_fluid"]
+    g.close()

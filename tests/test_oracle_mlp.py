@@ -173,3 +173,56 @@ def test_closure_judge_floor_near_equilibrium(orc, mlp):
         yo = np.tile(y / np.linalg.norm(y) * size, (len(f), 1))
         _, fell = mlp.collide(p, f, 0.6, y_override=yo)
         assert (fell == expect_fall).all(), size
+
+
+def test_forward_hand_computed_saturated_network(mlp):
+    """forward() on a network built so that every pre-activation is 0 or
+    +-15 / +-30: there the tanh-form GELU is exactly ReLU in FP64 (tanh
+    saturates to +-1 beyond |t| ~ 19), so the output follows from the
+    wiring alone.  The wiring uses shifts of the unit index (non-symmetric
+    weight matrices), a bias unit and non-trivial standardization, so a
+    transposed weight matrix, a misplaced bias or a standardization applied
+    the wrong way round changes the result.
+
+    Wiring (x = standardized input, entries in {-1, 0, 1}):
+      layer 1: unit j < 19 sees 30 x_j; unit 63 is a bias unit (b1 = 30);
+               unit 51 sees 30 x_1 - 15 (x_1 = -1: silent);
+      layer 2: unit (j + 1) mod 19 sees unit j, minus 15 from the bias unit,
+               so it fires (value 15) iff x_j = 1; unit 40 is a bias unit
+               (b2 = 7.5); unit 41 sees unit 51 plus 15;
+      layer 3: output i reads 2 x unit (i + 3) mod 19, plus 0.25 x unit 40,
+               plus 0.125 x unit 41, plus b3_i = i / 8;
+      then y = yt * out_std + out_mean."""
+    W1 = np.zeros((19, 64)); b1 = np.zeros(64)
+    W2 = np.zeros((64, 64)); b2 = np.zeros(64)
+    W3 = np.zeros((64, 19)); b3 = np.arange(19) / 8.0
+    for j in range(19):
+        W1[j, j] = 30.0
+        W2[j, (j + 1) % 19] = 1.0
+        W2[63, (j + 1) % 19] = -0.5
+    b1[63] = 30.0
+    W1[1, 51], b1[51] = 30.0, -15.0
+    W2[51, 41], b2[41] = 1.0, 15.0
+    b2[40] = 7.5
+    for i in range(19):
+        W3[(i + 3) % 19, i] = 2.0
+        W3[40, i] = 0.25
+        W3[41, i] = 0.125
+    in_mean = (np.arange(19) - 9) / 16.0
+    in_std = np.where(np.arange(19) % 2 == 0, 2.0, 0.25)
+    out_mean = np.full(19, -1.0)
+    out_std = np.where(np.arange(19) % 3 == 0, 4.0, 0.5)
+    p = mlp.Params(W1, b1, W2, b2, W3, b3, in_mean=in_mean, in_std=in_std, out_mean=out_mean,
+                   out_std=out_std)
+    v = np.array([1, -1, 0, 1, 1, 0, -1, 1, 0, 0, 1, -1, -1, 1, 0, 1, 0, 0, 1], np.float64)
+    g = in_mean + in_std * v  # standardizes back to v exactly (powers of two)
+    y = mlp.forward(p, g[None])[0]
+    want = np.zeros(19)
+    for i in range(19):
+        s = (i + 3) % 19          # layer-2 unit read by output i ...
+        j = (s - 1) % 19          # ... fires iff input j is +1
+        unit = 15.0 if v[j] == 1 else 0.0
+        unit41 = (15.0 if v[1] == 1 else 0.0) + 15.0
+        yt = 2.0 * unit + 0.25 * 7.5 + 0.125 * unit41 + i / 8.0
+        want[i] = yt * out_std[i] + out_mean[i]
+    assert np.array_equal(y, want), (y, want)

@@ -46,7 +46,7 @@ def test_multires_mass_exactly_conserved(orc, levels, n, collision):
     g = orc.MultiresGrid(*n, levels=levels, level_map=lm, tau_coarsest=0.56, collision=collision)
     f = random_state(g, 3)
     m0 = g.mass(f)
-    f = g.run(f, 12)
+    f = g.run(f, 200)  # 200 coarse steps
     m1 = g.mass(f)
     assert abs(m1 - m0) / m0 < 1e-13, (m0, m1)
 
@@ -60,7 +60,7 @@ def test_multires_mass_with_obstacle(orc):
     f = random_state(g, 5)
     f[0][fluid == 0] = 0.0
     m0 = g.mass(f)
-    f = g.run(f, 10)
+    f = g.run(f, 200)  # 200 coarse steps
     assert abs(g.mass(f) - m0) / m0 < 1e-13
 
 
@@ -149,3 +149,92 @@ def test_multires_lid_cavity_mass_exactly_conserved(orc):
     # the lid drives the flow: momentum along x appears on the finest level
     _, u0 = g.macroscopic(f)[0]
     assert np.max(u0[..., 0]) > 1e-3
+
+
+# ---------------------------------------------- multires index-map builder ---
+
+def test_multires_jump_voxels_of_a_refined_slab_closed_form(orc):
+    """Two levels in a periodic 64x16x16 box, the finest level on the slab
+    16 <= x < 32.  Distance-0 voxels: the two fine layers x = 16 and x = 31
+    (16 x 16 each) and the two coarse layers next to the slab, coarse x = 7
+    and x = 16 (8 x 8 each); jump blocks: fine block columns bx = 4 and 7
+    (4 x 4 blocks each), coarse bx = 1 and 4 (2 x 2 each)."""
+    n = (64, 16, 16)
+    lm = np.ones((16, 16, 64), np.uint8)
+    lm[:, :, 16:32] = 0
+    (a0, j0), (a1, j1) = orc.multires_level_masks(*n, 2, (True, True, True), lm)
+    assert a0.sum() == 16 * 16 * 16 and a1.sum() == 32 * 8 * 8 - 8 * 8 * 8
+    want0 = np.zeros_like(j0)
+    want0[:, :, [16, 31]] = True
+    want1 = np.zeros_like(j1)
+    want1[:, :, [7, 16]] = True
+    assert np.array_equal(j0, want0) and np.array_equal(j1, want1)
+    maps = orc.build_multires_maps(*n, 2, (True, True, True), lm, None, [orc.BB] * 6)
+    assert maps[0]["groups4"] == (2 * 4 * 4, 0, 0, 4 * 4 * 4 - 2 * 4 * 4)
+    assert maps[1]["groups4"][0] == 2 * 2 * 2
+    assert sorted(set(int(c) for c in maps[0]["coords"][:32, 0])) == [4, 7]
+    assert sorted(set(int(c) for c in maps[1]["coords"][:8, 0])) == [1, 4]
+
+
+def _jump_by_shifts(active_levels, lm, l, periodic):
+    """Second formulation of distance 0: the level-l territory array shifted
+    by each of the 18 face/edge offsets (np.roll; non-periodic axes padded
+    with 'same level' so sources outside the box never count)."""
+    s = 1 << l
+    terr = lm[::s, ::s, ::s].astype(np.int16)
+    act = active_levels
+    jump = np.zeros(act.shape, bool)
+    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+            if 1 <= abs(dx) + abs(dy) + abs(dz) <= 2]
+    assert len(offs) == 18
+    for dx, dy, dz in offs:
+        t = terr
+        for ax, d in ((2, dx), (1, dy), (0, dz)):
+            if d == 0:
+                continue
+            t = np.roll(t, d, axis=ax)
+            if not periodic[2 - ax]:
+                idx = [slice(None)] * 3
+                idx[ax] = 0 if d > 0 else -1
+                t[tuple(idx)] = l
+        jump |= act & (t != l)
+    return jump
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_multires_jump_voxels_match_shift_formulation(orc, seed):
+    rng = np.random.default_rng(seed)
+    levels = 2 + seed % 2
+    n = (64, 32, 32) if levels == 3 else (32, 32, 32)
+    periodic = (bool(seed & 1), True, seed != 2)
+    centre = rng.uniform(8, 24, 3) * np.array(n) / 32
+    lm = blob_level_map(n, levels, tuple(centre), rng.uniform(3, 6), periodic=periodic)
+    for l, (act, jmp) in enumerate(orc.multires_level_masks(*n, levels, periodic, lm)):
+        assert np.array_equal(jmp, _jump_by_shifts(act, lm, l, periodic)), l
+        assert (jmp <= act).all()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_multires_block_maps_neighbours_brute_force(orc, seed):
+    """Per level: the neighbour tables against the O(n^2) scan, Morton order
+    inside each of the groups [jump | boundary | masked | full], and the
+    jump group equal to the blocks holding a distance-0 voxel."""
+    levels, n = 3, (64, 32, 32)
+    periodic = (False, True, True)
+    rng = np.random.default_rng(50 + seed)
+    lm = blob_level_map(n, levels, (rng.uniform(24, 40), 16, 16), 5.0, band=6.0, periodic=periodic)
+    faces = [orc.REG_VEL, orc.REG_PRES, orc.BB, orc.BB, orc.BB, orc.BB]
+    masks = orc.multires_level_masks(*n, levels, periodic, lm)
+    maps = orc.build_multires_maps(*n, levels, periodic, lm, None, faces)
+    for l, m in enumerate(maps):
+        nb = tuple(k >> (l + 2) for k in n)
+        assert np.array_equal(orc.brute_force_neighbours(m["coords"], periodic, nb), m["nbr"])
+        keys = [orc.morton_key(*c) for c in m["coords"]]
+        lo = 0
+        for cnt in m["groups4"]:
+            assert keys[lo:lo + cnt] == sorted(keys[lo:lo + cnt])
+            lo += cnt
+        jmp = masks[l][1]
+        holds = [bool(jmp[z * 4:z * 4 + 4, y * 4:y * 4 + 4, x * 4:x * 4 + 4].any()) for x, y, z in m["coords"]]
+        nj = m["groups4"][0]
+        assert all(holds[:nj]) and not any(holds[nj:])
