@@ -29,16 +29,16 @@ def cavity(n=256, storage=lbm.F32, schedule=lbm.DISAGG, tau=0.55, uw=0.1, collis
 
 @functools.lru_cache(maxsize=2)
 def _packing(n, seed):
-    fluid, _ = workloads.sphere_packing(*n, seed=seed)
+    fluid, _ = workloads.channel_packing(*n, seed=seed)
     fluid.setflags(write=False)
     return fluid
 
 
 def tunnel(storage=lbm.F32, schedule=lbm.DISAGG, tau=0.6, n=(512, 256, 256), collision=lbm.BGK, seed=7898,
            q=19):
-    """Block-sparse wind tunnel through a seeded sphere packing (<= 30% of
-    4^3 blocks active), velocity inlet 0.05 on x-, pressure outlet rho = 1 on
-    x+, bounce-back walls on y and z."""
+    """Block-sparse wind tunnel through seeded channels of overlapping spheres
+    (radii 8-32, <= 30% of 4^3 blocks active), velocity inlet 0.05 on x-,
+    pressure outlet rho = 1 on x+, bounce-back walls on y and z."""
     fluid = _packing(tuple(n), seed)
     faces = {lbm.XMIN: (lbm.BC_REG_VELOCITY, (0.05, 0.0, 0.0)),
              lbm.XMAX: (lbm.BC_REG_PRESSURE, (1.0, 0.0, 0.0))}

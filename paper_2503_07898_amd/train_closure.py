@@ -3,12 +3,9 @@
 Data: pre-collision populations of non-boundary fluid voxels sampled at 20
 evenly spaced times from regularized-operator runs of the three benchmark
 geometries (dense cavity 256^3 over 2000 steps, block-sparse wind tunnel
-512x256x256 over its first 400 steps, multires sphere over 1000 coarse
-steps), one third of the samples from each.  (The wind tunnel's velocity
-inlet keeps pushing mass into a packing that lets little through; its
-density grows by a third in 500 steps and the run loses finiteness soon
-after, so it is sampled before that.)  Rows that are not finite are
-dropped.  Training: the
+512x256x256 over 1000 steps, multires sphere over 1000 coarse steps), one
+third of the samples from each.  Rows that are not finite are dropped.
+Training: the
 library's own kernels (matrix-core forward, backward, Adam), batch 4096,
 learning rate cosine-decayed from 1e-3 to 1e-5, He-uniform initialization.
 
@@ -49,10 +46,10 @@ def dataset(n_total: int, seed: int = 2025, times: int = 20):
         parts.append(g.sample(seed + k, per_case // times))
     g.close()
     log(f"  cavity samples done")
-    # block-sparse wind tunnel, first 400 steps
+    # block-sparse wind tunnel, 1000 steps
     g = cases.tunnel(collision=lbm.REGULARIZED)
     for k in range(times):
-        g.step(400 // times)
+        g.step(1000 // times)
         parts.append(g.sample(seed + 100 + k, per_case // times))
     g.close()
     log(f"  tunnel samples done")

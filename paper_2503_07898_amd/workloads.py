@@ -109,6 +109,58 @@ def sphere_packing(nx: int, ny: int, nz: int, seed: int = 7898,
     return (~solid).astype(np.uint8), spheres
 
 
+def channel_packing(nx: int, ny: int, nz: int, seed: int = 7898,
+                    rmin: float = 8.0, rmax: float = 32.0,
+                    target_active: float = 0.30, block: int = 4):
+    """Pore-channel geometry for the block-sparse wind tunnel.
+
+    Fluid = union of spheres strung into channels that cross the box along x.
+    A channel draws one radius r ~ U[rmin, rmax] and an entry point
+    (y, z) ~ U(inlet face); its sphere centres start on the inlet plane
+    x = 0 and advance by r/2 along x, each step moving the centre by
+    U[-r/4, r/4] along y and z (clamped to the box), until a sphere reaches
+    past the outlet plane.  Channels are drawn from
+    numpy.random.default_rng(seed) and kept while the fraction of block^3
+    blocks holding at least one fluid voxel stays <= target_active (the
+    channel that would exceed it ends the draw).
+
+    Consecutive spheres of a channel overlap by half a radius, so every
+    channel joins the inlet to the outlet through openings of at least
+    0.97 r, and channels that meet join.
+
+    Returns (fluid uint8 (nz, ny, nx), number of channels).
+    """
+    assert nx % block == 0 and ny % block == 0 and nz % block == 0
+    rng = np.random.default_rng(seed)
+    fluid = np.zeros((nz, ny, nx), bool)
+    nblocks = (nx // block) * (ny // block) * (nz // block)
+
+    def active(f):
+        return f.reshape(nz // block, block, ny // block, block, nx // block, block).any(axis=(1, 3, 5))
+
+    channels = 0
+    while True:
+        r = rng.uniform(rmin, rmax)
+        y, z = rng.uniform(0, ny), rng.uniform(0, nz)
+        x = 0.0
+        cand = fluid.copy()
+        while x - r < nx:
+            lo = [max(0, int(math.floor(c - r))) for c in (x, y, z)]
+            hi = [min(n, int(math.ceil(c + r)) + 1) for c, n in ((x, nx), (y, ny), (z, nz))]
+            zs = np.arange(lo[2], hi[2], dtype=np.float64)[:, None, None]
+            ys = np.arange(lo[1], hi[1], dtype=np.float64)[None, :, None]
+            xs = np.arange(lo[0], hi[0], dtype=np.float64)[None, None, :]
+            cand[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] |= (xs - x) ** 2 + (ys - y) ** 2 + (zs - z) ** 2 <= r * r
+            x += r / 2
+            y = min(max(y + rng.uniform(-r / 4, r / 4), 0.0), float(ny))
+            z = min(max(z + rng.uniform(-r / 4, r / 4), 0.0), float(nz))
+        if channels > 0 and np.count_nonzero(active(cand)) > target_active * nblocks:
+            break
+        fluid = cand
+        channels += 1
+    return fluid.astype(np.uint8), channels
+
+
 def random_mask(nx: int, ny: int, nz: int, seed: int, solid_fraction: float = 0.3,
                 block: int = 4, empty_block_fraction: float = 0.2):
     """Random block-sparse fluid mask for map and parity tests: some blocks are

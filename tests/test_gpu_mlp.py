@@ -88,10 +88,18 @@ def test_forward_and_gradients_match_oracle(orc, mlpo):
     m.close()
 
 
-def test_closure_step_matches_oracle(orc, mlpo):
-    """One solver step with the closure against the oracle's closure
-    (stream, then collide with the same bf16-rounded weights), on a
-    non-equilibrium state of a regularized Taylor-Green run."""
+def bf16_round(x):
+    """Round float64 values to bfloat16 (round to nearest, ties to even) and
+    back, through float32 bit patterns."""
+    b = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def closure_case():
+    """A non-equilibrium state of a regularized Taylor-Green run (16^3) and a
+    network standardized on samples of it."""
     n, tau = 16, 0.6
     rho, u = workloads.taylor_green_3d(n, 0.05)
     src = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau, collision=lbm.REGULARIZED).bind()
@@ -103,35 +111,81 @@ def test_closure_step_matches_oracle(orc, mlpo):
     m = lbm.Mlp()
     m.set_params(lbm.flatten_params(workloads.mlp_he_uniform(9)))
     m.fit_standardization(data)
-    for storage, judge in ((lbm.F32, 0.0), (lbm.F16_SHIFTED, 0.0), (lbm.BF16_SHIFTED, 0.0), (lbm.F32, 0.01)):
-        m.set_judge(judge)
-        g = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau, storage=storage).bind()
-        g.set_collision(lbm.MLP, m)
-        g.write_populations(f0)
-        start = g.populations().cpu().numpy()  # the stored (rounded) state
-        m.fallbacks(reset=True)
-        g.step(1)
-        f1 = g.populations().cpu().numpy().T
-        fb = m.fallbacks()
-        g.close()
-        c, _, _ = orc.lattice()
-        pre = np.empty_like(start)
-        for i in range(19):
-            pre[i] = np.roll(start[i].reshape(n, n, n), shift=(c[i][2], c[i][1], c[i][0]),
-                             axis=(0, 1, 2)).reshape(-1)
-        p = oracle_params(mlpo, lbm.unflatten_params(m.params()), m.standardization())
-        ref, fell = mlpo.collide(p, pre.T, tau, judge=judge)
-        feq = np.array([orc.equilibrium(*orc.moments(ref[k])) for k in range(ref.shape[0])])
-        e = rel(f1 - feq, ref - feq)
-        _say(f"  storage {storage} judge {judge}: rel L2 of f* - f^eq vs oracle closure {e:.2e}, "
-             f"fallbacks gpu {fb} oracle {int(fell.sum())}")
-        # the compared part f* - f^eq is small next to the stored h = f* - w,
-        # so bfloat16's rounding of h (8 significant bits against binary16's
-        # 11) shows in it 8x more; its bar is the 2e-2 of the other bfloat16 tests
-        assert e < (2e-2 if storage == lbm.BF16_SHIFTED else 1e-2)
-        # decisions taken in different precisions may differ at the threshold
-        assert abs(fb - int(fell.sum())) <= max(2, fell.size // 200)
+    yield n, tau, f0, m
     m.close()
+
+
+def closure_step(orc, mlpo, closure_case, storage, judge):
+    """One GPU step with the closure and the oracle's closure applied to the
+    same stored (rounded) state: (gpu f*, oracle f*, oracle f^eq, fallbacks)."""
+    n, tau, f0, m = closure_case
+    m.set_judge(judge)
+    g = lbm.Grid(n, n, n, kind=lbm.DENSE, tau=tau, storage=storage).bind()
+    g.set_collision(lbm.MLP, m)
+    g.write_populations(f0)
+    start = g.populations().cpu().numpy()  # the stored (rounded) state
+    m.fallbacks(reset=True)
+    g.step(1)
+    f1 = g.populations().cpu().numpy().T
+    fb = m.fallbacks()
+    g.close()
+    c, _, _ = orc.lattice()
+    pre = np.empty_like(start)
+    for i in range(19):
+        pre[i] = np.roll(start[i].reshape(n, n, n), shift=(c[i][2], c[i][1], c[i][0]),
+                         axis=(0, 1, 2)).reshape(-1)
+    p = oracle_params(mlpo, lbm.unflatten_params(m.params()), m.standardization())
+    ref, fell = mlpo.collide(p, pre.T, tau, judge=judge)
+    feq = np.array([orc.equilibrium(*orc.moments(ref[k])) for k in range(ref.shape[0])])
+    return f1, ref, feq, fb, int(fell.sum()), fell.size
+
+
+# bfloat16 storage rounds the stored h = f* - w to 8 significant bits; the
+# compared part f* - f^eq is small next to h, so that rounding shows in it:
+# 1.71e-2 measured against the 1e-2 bar (binary16: 4.0e-3).  The case is an
+# expected failure; the test after it shows that the difference is the
+# storage rounding of the output and nothing else.
+@pytest.mark.parametrize("storage,judge", [
+    (lbm.F32, 0.0), (lbm.F16_SHIFTED, 0.0),
+    pytest.param(lbm.BF16_SHIFTED, 0.0, marks=pytest.mark.xfail(
+        reason="bfloat16 storage: 1.71e-2 measured against the 1e-2 bar", strict=False)),
+    (lbm.F32, 0.01),
+])
+def test_closure_step_matches_oracle(orc, mlpo, closure_case, storage, judge):
+    """One solver step with the closure against the oracle's closure
+    (stream, then collide with the same bf16-rounded weights), on a
+    non-equilibrium state of a regularized Taylor-Green run."""
+    f1, ref, feq, fb, fell, size = closure_step(orc, mlpo, closure_case, storage, judge)
+    e = rel(f1 - feq, ref - feq)
+    _say(f"  storage {storage} judge {judge}: rel L2 of f* - f^eq vs oracle closure {e:.2e}, "
+         f"fallbacks gpu {fb} oracle {fell}")
+    # decisions taken in different precisions may differ at the threshold
+    assert abs(fb - fell) <= max(2, size // 200)
+    assert e < 1e-2
+
+
+def test_closure_step_bf16_is_output_rounding(orc, mlpo, closure_case):
+    """With bfloat16 storage, every stored output h = f* - w of the GPU step
+    equals the oracle closure's output rounded to bfloat16 (nearest, ties to
+    even) or one of its two neighbours: the difference measured by the test
+    above is the rounding of the output, where the GPU's FP32 f* and the
+    oracle's FP64 f* fall on the two sides of a rounding boundary."""
+    f1, ref, feq, _, _, _ = closure_step(orc, mlpo, closure_case, lbm.BF16_SHIFTED, 0.0)
+    _, w, _ = orc.lattice()
+    w = np.asarray(w)[None, :]
+
+    def ordered(h):  # bfloat16 bit patterns as integers that count ulps
+        b = (np.asarray(h, np.float32).view(np.uint32) >> 16).astype(np.int64)
+        return np.where(b & 0x8000, -(b & 0x7FFF), b)
+
+    got = ordered(f1 - w)  # the stored values (exact: f1 is w + h in FP64)
+    assert np.array_equal(bf16_round(f1 - w), f1 - w)
+    want = ordered(bf16_round(ref - w))
+    d = np.abs(got - want)
+    frac = float(np.count_nonzero(d)) / d.size
+    _say(f"  bfloat16 outputs: {100 * frac:.2f}% one ulp from the oracle's rounded output, max {int(d.max())} ulp")
+    assert d.max() <= 1
+    assert frac < 0.02
 
 
 def regularized_tg_samples(n_samples, seed, n=32, steps=40):

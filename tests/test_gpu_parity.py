@@ -166,12 +166,17 @@ def tunnel(n=(64, 32, 32), seed=7, rmin=3.0, rmax=8.0, target=0.6):
     return fluid, faces
 
 
-# bfloat16 keeps 8 significant bits against binary16's 11, so its rounding
-# error per stored population is 8x larger; on the wind tunnel it lands at
-# about 1.0e-2 after 150 steps (binary16: well under 1e-2).  Its bar here is
-# 2e-2, and the measured value is reported, not hidden.
-@pytest.mark.parametrize("collision", [lbm.BGK, lbm.REGULARIZED])
-@pytest.mark.parametrize("storage,bar", [(lbm.F32, 1e-5), (lbm.F16_SHIFTED, 1e-2), (lbm.BF16_SHIFTED, 2e-2)])
+# bfloat16 storage keeps 8 significant bits of f - w (binary16 keeps 11):
+# with BGK it measures 1.019e-2 here after 150 steps, above the 1e-2 bar, so
+# that case is an expected failure; binary16 is the 16-bit form that meets
+# the bar everywhere.
+@pytest.mark.parametrize("storage,bar,collision", [
+    (lbm.F32, 1e-5, lbm.BGK), (lbm.F16_SHIFTED, 1e-2, lbm.BGK),
+    pytest.param(lbm.BF16_SHIFTED, 1e-2, lbm.BGK, marks=pytest.mark.xfail(
+        reason="bfloat16 storage: 1.019e-2 measured against the 1e-2 bar", strict=False)),
+    (lbm.F32, 1e-5, lbm.REGULARIZED), (lbm.F16_SHIFTED, 1e-2, lbm.REGULARIZED),
+    (lbm.BF16_SHIFTED, 1e-2, lbm.REGULARIZED),
+])
 def test_sparse_tunnel_vs_oracle(orc, storage, bar, collision):
     n, steps, tau = (64, 32, 32), 150, 0.6
     _say(f"tunnel {n} storage={storage} collision={collision}")
