@@ -181,6 +181,21 @@ lbm_status lbm_read_macroscopic(lbm_grid *g, int32_t level, void *rho_dev, void 
  * (fixed-order two-pass sum). */
 lbm_status lbm_reduce(lbm_grid *g, double *out5_dev, void *stream);
 
+/* lbm_reduce for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same sums, bitwise equal to lbm_reduce's, computed without the
+ * reduction scratch of the grid's workspace.  Its chunk sums live in a
+ * device array of the library, 4096 rows of five doubles (160 KiB) per GPU,
+ * held until the process ends; grids of more than 4096 x 2048 x 64 =
+ * 536,870,912 slots (all levels together) are rejected with
+ * LBM_ERR_INVALID_ARG, grids of more than 8 levels with LBM_ERR_UNSUPPORTED.
+ * Allocates nothing (no hipMalloc, no host-side device allocation).  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from different threads) race; calls on one
+ * stream are ordered.  out5_dev: five doubles in device memory, written
+ * asynchronously on `stream`. */
+lbm_status lbm_reduce_noalloc(lbm_grid *g, double *out5_dev, void *stream);
+
 /* Health check: runs the reductions above into the grid's workspace, waits
  * for the stream and returns LBM_ERR_NUMERIC if any sum is not finite.  A
  * NaN or infinite population anywhere makes the mass sum non-finite, so

@@ -79,12 +79,13 @@ struct LatticeLaunchers {
   hipError_t (*write_pop)(const SlotArgs &, const double *, hipStream_t);
   hipError_t (*reduce_partial)(const SlotArgs &, double, double *, hipStream_t);
   hipError_t (*reduce_final)(const double *, int64_t, double *, double *, hipStream_t);
+  hipError_t (*reduce_noalloc)(const ReduceLevels &, double *, hipStream_t);
 };
 #define LBM_LAUNCHERS_OF(ns)                                                                          \
   LatticeLaunchers {                                                                                  \
     &ns::launch_one, &ns::launch_init_equilibrium, &ns::launch_read_macroscopic,                      \
         &ns::launch_read_populations, &ns::launch_write_populations, &ns::launch_reduce_partial,      \
-        &ns::launch_reduce_final                                                                      \
+        &ns::launch_reduce_final, &ns::launch_reduce_noalloc                                          \
   }
 
 // Multires levels up to this many blocks run each update as one launch by
@@ -641,6 +642,29 @@ lbm_status lbm_reduce(lbm_grid *g, double *out5, void *stream) {
   if (e == hipSuccess)
     e = g->ops.reduce_final(partial, g->partial_rows, (double *)(g->ws + g->off_mid), out5, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "reduce");
+  return LBM_OK;
+}
+
+lbm_status lbm_reduce_noalloc(lbm_grid *g, double *out5, void *stream) {
+  if (!g || !out5) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (g->state < kCommitted) return fail(LBM_ERR_STATE, "commit, bind and initialise the grid first");
+  if ((int)g->lv.size() > kReduceMaxLevels) return fail(LBM_ERR_UNSUPPORTED, "more than %d levels", kReduceMaxLevels);
+  const int64_t nmid = reduce_mid_rows(g->partial_rows);
+  if (nmid > kNoAllocMidRows)
+    return fail(LBM_ERR_INVALID_ARG, "grid too large for lbm_reduce_noalloc: %lld slots, limit %lld",
+                (long long)g->partial_rows * 64, (long long)(kNoAllocMidRows * kReduceChunk * 64));
+  if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
+  ReduceLevels R{};
+  R.nlevels = (int32_t)g->lv.size();
+  for (int l = 0; l < R.nlevels; ++l) {
+    const LevelRT &r = g->lv[l];
+    R.a[l] = slot_args(g, r);
+    R.weight[l] = (double)(1ll << (3 * l));
+    R.row0[l] = r.partial_row0;
+  }
+  R.row0[R.nlevels] = g->partial_rows;
+  hipError_t e = g->ops.reduce_noalloc(R, out5, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce_noalloc");
   return LBM_OK;
 }
 

@@ -119,6 +119,19 @@ struct SlotArgs {
   int32_t blocked;           // 1: block-interleaved populations, 0: planes of S
 };
 
+// The reduction without workspace scratch (lbm_reduce_noalloc): the same
+// fixed-order sums, the first two passes fused per chunk of kReduceChunk
+// rows, the chunk sums kept in a device array of kNoAllocMidRows rows of five
+// doubles that the library holds for the life of the process.
+constexpr int kReduceMaxLevels = 8;
+constexpr int64_t kNoAllocMidRows = 4096;
+struct ReduceLevels {
+  SlotArgs a[kReduceMaxLevels];
+  double weight[kReduceMaxLevels];
+  int64_t row0[kReduceMaxLevels + 1];  // first partial row of each level; row0[nlevels] = all rows
+  int32_t nlevels;
+};
+
 // Launchers built once per lattice (step_kernels.hip and util_kernels.hip
 // are compiled for D3Q19 into k19 and for D3Q27 into k27).
 #define LBM_DECLARE_LATTICE_LAUNCHERS                                                                  \
@@ -130,7 +143,8 @@ struct SlotArgs {
   hipError_t launch_write_populations(const SlotArgs &A, const double *f, hipStream_t s);               \
   /* partial sums per 64-slot group (weighted by `weight`) into partial[first_row..] */                 \
   hipError_t launch_reduce_partial(const SlotArgs &A, double weight, double *partial, hipStream_t s);   \
-  hipError_t launch_reduce_final(const double *partial, int64_t rows, double *mid, double *out5, hipStream_t s);
+  hipError_t launch_reduce_final(const double *partial, int64_t rows, double *mid, double *out5, hipStream_t s); \
+  hipError_t launch_reduce_noalloc(const ReduceLevels &R, double *out5, hipStream_t s);
 
 LBM_NAMESPACE_K19 {
 LBM_DECLARE_LATTICE_LAUNCHERS

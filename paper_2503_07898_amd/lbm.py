@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
             "lbm_step": ([vp, i32, vp], i32),
             "lbm_read_macroscopic": ([vp, i32, vp, vp, i32, vp], i32),
             "lbm_reduce": ([vp, vp, vp], i32),
+            "lbm_reduce_noalloc": ([vp, vp, vp], i32),
             "lbm_read_populations": ([vp, i32, vp, vp], i32),
             "lbm_write_populations": ([vp, i32, vp, vp], i32),
             "lbm_get_index_map": ([vp, i32, i32, vp, ctypes.POINTER(sz)], i32),
@@ -162,6 +163,10 @@ def lbm_read_macroscopic(g, level: int, rho_ptr: int, u_ptr: int, f64: bool, str
 
 def lbm_reduce(g, out_ptr: int, stream=None) -> None:
     check(lib().lbm_reduce(g, out_ptr, _stream_ptr(stream)))
+
+
+def lbm_reduce_noalloc(g, out_ptr: int, stream=None) -> None:
+    check(lib().lbm_reduce_noalloc(g, out_ptr, _stream_ptr(stream)))
 
 
 def lbm_read_populations(g, level: int, f_ptr: int, stream=None) -> None:
@@ -389,6 +394,15 @@ class Grid:
         import torch
         out = torch.empty(5, dtype=torch.float64, device=self.device)
         lbm_reduce(self.h, out.data_ptr())
+        return out
+
+    def reduce_noalloc(self, out=None):
+        """lbm_reduce_noalloc into `out` (5 FP64 on the device; allocated here
+        when None)."""
+        import torch
+        if out is None:
+            out = torch.empty(5, dtype=torch.float64, device=self.device)
+        lbm_reduce_noalloc(self.h, out.data_ptr())
         return out
 
     def index_map(self, which: int, level: int = 0) -> np.ndarray:
