@@ -44,6 +44,11 @@ BYTES_PER_UPDATE = {0: 152, 1: 76, 2: 76}  # FP32, FP16-shifted, BF16-shifted
 # multiply-adds with the 19-wide layers padded to 32
 MLP_MFMA_FLOPS = 2 * (32 * 64 + 64 * 64 + 64 * 32)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+# vector ALU issue without packed FP32 (which this library never emits): a
+# wave64 instruction occupies one of a CU's 4 SIMDs (16 lanes) for 4 cycles,
+# so 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
+STORE_NAME = {0: "StoreF32", 1: "StoreF16", 2: "StoreBF16"}
 
 
 def log(msg: str) -> None:
@@ -102,7 +107,7 @@ def time_launch(torch, lbm, g, k: int, reps: int) -> float:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("device_common.h", "step_kernels.hip", "launch.h", "lattice.h"):
+    for f in ("device_common.h", "step_kernels.hip", "launch.h", "lattice.h", "mlp_device.h"):
         with open(os.path.join(ROOT, "paper_2503_07898_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -121,6 +126,22 @@ def measured_traffic(kernel: str):
     if not e or e.get("source_hash") != source_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def measured_valu(kernel: str):
+    """Vector instructions per wave of `kernel` (SQ_INSTS_VALU / SQ_WAVES)
+    from the committed rocprofv3 counter summary, or None if absent or taken
+    on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "valu.json")
+    try:
+        with open(p) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("valu_insts_per_wave")
 
 
 def cpu_baseline(workloads, budget_s: float = 15.0):
@@ -241,7 +262,7 @@ def main(argv=None) -> int:
 
     arms = {}
     if args.arms in ("all", "closure", "storage"):
-        def arm(name, make, steps, bytes_per_update, interior=False):
+        def arm(name, make, steps, bytes_per_update, interior=None):
             log(name)
             gg = make()
             n_up = getattr(gg, "updates_per_step", None) or gg.n
@@ -257,7 +278,7 @@ def main(argv=None) -> int:
                 arms[name]["slots"] = slots
                 arms[name]["hbm_frac_slot"] = round(m * 1e6 * slots / n_up * bytes_per_update / 1e9
                                                     / HBM_PEAK_GBS, 4)
-            if interior:
+            if interior is not None:
                 # the interior (full-group) launch alone: HBM and matrix-core shares
                 _, _, _, nf, _ = gg.index_map(lbm.MAP_GROUPS)
                 t = time_launch(torch, lbm, gg, gg.launches().index(int(nf)), 20)
@@ -268,6 +289,15 @@ def main(argv=None) -> int:
                     "hbm_frac": round(ups * bytes_per_update / t / 1e9 / HBM_PEAK_GBS, 4),
                     "mfma_TFLOPs_bf16": round(ups * MLP_MFMA_FLOPS / t / 1e12, 1),
                     "mfma_frac": round(ups * MLP_MFMA_FLOPS / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
+                # the binding resource of the closure: vector-instruction issue
+                # (one wave per block), from the counted instructions per wave
+                kname = f"lbm::k19::k_block_interior_mlp<lbm::k19::{STORE_NAME[interior]}, false>"
+                vpw = measured_valu(kname)
+                il = arms[name]["interior_launch"]
+                il["valu_insts_per_wave"] = vpw
+                il["valu_lane_Tops"] = None if vpw is None else round(vpw * 64 * int(nf) / t / 1e12, 2)
+                il["valu_frac"] = None if vpw is None else round(vpw * 64 * int(nf) / t / VALU_LANE_PEAK, 4)
+                il["bound"] = "valu"
             gg.close()
             torch.cuda.empty_cache()
 
@@ -283,11 +313,15 @@ def main(argv=None) -> int:
                             (lbm.DISAGG_BITMASK, "disagg_bitmask")):
                 arm(f"tunnel512x256x256_{['f32', 'f16'][st]}_{nm}",
                     lambda st=st, sch=sch: cases.tunnel(storage=st, schedule=sch), 50, bpu)
+        # multires schedules: the unfused baseline, the paper's own (uniform
+        # blocks fused, jump blocks unfused) and every group fused
+        mr_schedules = ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"),
+                        (lbm.DISAGG_UNIFORM_FUSED, "paper_uniform_fused"), (lbm.DISAGG, "disagg_fused"))
         for st, bpu in ((lbm.F32, 152), (lbm.F16_SHIFTED, 76)):
-            for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"), (lbm.DISAGG, "disagg_fused")):
+            for sch, nm in mr_schedules:
                 arm(f"multires_sphere_c128_{['f32', 'f16'][st]}_{nm}",
                     lambda st=st, sch=sch: cases.multires_sphere(storage=st, schedule=sch), 50, bpu)
-        for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"), (lbm.DISAGG, "disagg_fused")):
+        for sch, nm in mr_schedules:
             arm(f"multires_sphere_c256_f32_{nm}",
                 lambda sch=sch: cases.multires_sphere(schedule=sch, scale=2), 20, 152)
         # D3Q27 (the lattice of the paper's block-sparse register study):
@@ -300,8 +334,12 @@ def main(argv=None) -> int:
         arm("cavity256_d3q27_f32_disagg", lambda: cases.cavity(q=27), 50, 216)
         # the paper's own multires benchmark shape: lid-driven cavity, 512^3
         # finest box, 77.6M / 4.09M / 0.37M voxels on levels 0 / 1 / 2
-        for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"), (lbm.DISAGG, "disagg_fused")):
+        for sch, nm in mr_schedules:
             arm(f"multires_cavity512_f32_{nm}", lambda sch=sch: cases.multires_cavity(schedule=sch), 10, 152)
+        # the 4-level rows of table multiResLbm (77.6M / 2.98M / 0.48M / 0.004M voxels)
+        for sch, nm in mr_schedules:
+            arm(f"multires_cavity512_4lvl_f32_{nm}",
+                lambda sch=sch: cases.multires_cavity(schedule=sch, levels=4), 10, 152)
         arm("taylor_green256_re1600_f32_regularized",
             lambda: cases.taylor_green(collision=lbm.REGULARIZED), 100, 152)
         arm("taylor_green256_re1600_f32_bgk", lambda: cases.taylor_green(collision=lbm.BGK), 100, 152)
@@ -318,7 +356,8 @@ def main(argv=None) -> int:
                            ("cavity256_f32_mlp", lambda: cases.cavity()),
                            ("cavity256_f16_mlp", lambda: cases.cavity(storage=lbm.F16_SHIFTED))):
             net.fallbacks(reset=True)
-            arm(name, lambda make=make: with_net(make()), 50, 76 if "f16" in name else 152, interior=True)
+            arm(name, lambda make=make: with_net(make()), 50, 76 if "f16" in name else 152,
+                interior=lbm.F16_SHIFTED if "f16" in name else lbm.F32)
             arms[name]["closure"] = which
             arms[name]["fallbacks"] = net.fallbacks()
         net.close()

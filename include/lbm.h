@@ -95,8 +95,22 @@ typedef enum { LBM_BGK = 0, LBM_REGULARIZED = 1, LBM_MLP = 2 } lbm_collision;
  *   block and skip the blocks of the other kind at run time.  Boundary
  *   values reach the boundary kernel through indirect indexing: a 32-bit id
  *   per voxel slot selects the voxel's entry in a contiguous buffer of
- *   boundary-voxel records.  Not with LBM_MLP, not for sampling. */
-typedef enum { LBM_PLAIN_SINGLE_KERNEL = 0, LBM_DISAGG = 1, LBM_DISAGG_BITMASK = 2 } lbm_schedule;
+ *   boundary-voxel records.  Not with LBM_MLP, not for sampling.
+ * LBM_DISAGG_UNIFORM_FUSED: multires only, the paper's own multires
+ *   schedule ("Improving Multi-resolution LBM Kernel Fusion"): at every
+ *   level above the finest, blocks of the uniform groups run the fused
+ *   collide-and-stream kernels while jump blocks keep separate streaming
+ *   (their gathers, stored) and collision kernels; the finest level is
+ *   fused throughout, as in the other two multires schedules.  LBM_DISAGG
+ *   fuses the jump blocks as well (their explosion and coalescence sources
+ *   are precomputed gathers).  All three give the same FP32 result bit for
+ *   bit. */
+typedef enum {
+  LBM_PLAIN_SINGLE_KERNEL = 0,
+  LBM_DISAGG = 1,
+  LBM_DISAGG_BITMASK = 2,
+  LBM_DISAGG_UNIFORM_FUSED = 3
+} lbm_schedule;
 
 typedef struct {
   lbm_grid_kind kind;
@@ -295,6 +309,17 @@ lbm_status lbm_mlp_gradients(lbm_mlp *m, const float *f_dev, const int64_t *idx_
  * with learning rate lr on the FP32 master weights, then the bf16 copy. */
 lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f_dev, const int64_t *idx_dev, int64_t n,
                               float lr, int32_t t, double *loss_dev, void *stream);
+/* Adam step t (t >= 1, learning rate lr > 0; beta 0.9 / 0.999, eps 1e-8)
+ * on caller-supplied gradients grads_dev [LBM_MLP_PARAMS] (FP32, device;
+ * e.g. from lbm_mlp_gradients, possibly combined by the caller), then the
+ * bf16 copy of the weights.  Asynchronous on `stream`. */
+lbm_status lbm_mlp_adam(lbm_mlp *m, const float *grads_dev, float lr, int32_t t, void *stream);
+/* Seeded initial weights on the device: He-uniform
+ * U(-sqrt(6/fan_in), +sqrt(6/fan_in)) per layer (fan_in 19, 64, 64), zero
+ * biases; weight p takes 53 bits of splitmix64(seed ^ splitmix64(p))
+ * (Steele, Lea and Flood 2014), so a seed fixes the network on any device.
+ * Asynchronous on `stream`; optimizer state is left as it is. */
+lbm_status lbm_mlp_init_params(lbm_mlp *m, uint64_t seed, void *stream);
 /* Tolerance of the run-time judge (default 0.01): a voxel keeps the
  * closure's update only if |P(y) - f1/rho|_2^2 <= rel_tol^2 (|f1/rho|_2^2 +
  * |out_std|_2^2), with f1 the regularized operator's non-equilibrium part

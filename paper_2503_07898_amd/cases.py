@@ -76,20 +76,26 @@ def multires_sphere(storage=lbm.F32, schedule=lbm.DISAGG, scale=1, collision=lbm
     return g
 
 
-def multires_cavity(n=512, storage=lbm.F32, schedule=lbm.DISAGG, tau=0.52, uw=0.1, collision=lbm.BGK):
+def multires_cavity(n=512, storage=lbm.F32, schedule=lbm.DISAGG, tau=0.52, uw=0.1, collision=lbm.BGK,
+                    levels=3, shells=None):
     """Multi-resolution lid-driven cavity: closed n^3 box (finest
-    resolution), 3 levels refined towards the walls (57.8% / 24.4% / 17.8% of
-    the volume on levels 0 / 1 / 2 at n = 512), bounce-back walls, lid z+
-    moving with (uw, 0, 0) on the finest level, tau at the coarsest level."""
-    lm = workloads.multires_cavity(n)
+    resolution) refined towards the walls, bounce-back walls, lid z+ moving
+    with (uw, 0, 0) on the finest level, tau at the coarsest level.  Three
+    levels by default (57.8% / 24.4% / 17.8% of the volume on levels
+    0 / 1 / 2 at n = 512: 77.6M / 4.09M / 0.37M voxels); with levels=4 the
+    shells (64, 32, 96) at n = 512 give 77.6M / 2.98M / 0.48M / 0.004M
+    voxels (the 4-level rows of table multiResLbm: 73 / 3 / 0.5 / 0.003)."""
+    if levels == 4 and shells is None:
+        shells = (n // 8, n // 16, 3 * n // 16)
+    lm = workloads.multires_cavity(n, levels=levels, shells=shells)
     faces = {f: (lbm.BC_BOUNCE_BACK, (0, 0, 0)) for f in range(6)}
     faces[lbm.ZMAX] = (lbm.BC_MOVING_WALL, (uw, 0.0, 0.0))
-    g = lbm.Grid(n, n, n, kind=lbm.MULTIRES, levels=3, level_map=lm, periodic=(False,) * 3,
+    g = lbm.Grid(n, n, n, kind=lbm.MULTIRES, levels=levels, level_map=lm, periodic=(False,) * 3,
                  faces=faces, tau=tau, storage=storage, schedule=schedule, collision=collision).bind()
-    for l in range(3):
+    for l in range(levels):
         N = g.n_level(l)
         g.init_equilibrium(np.ones(N), np.zeros((3, N)), level=l)
-    g.updates_per_step = sum(g.n_level(l) * 2 ** (2 - l) for l in range(3))
+    g.updates_per_step = sum(g.n_level(l) * 2 ** (levels - 1 - l) for l in range(levels))
     return g
 
 

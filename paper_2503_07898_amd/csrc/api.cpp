@@ -65,7 +65,8 @@ struct lbm_mlp {
   size_t total = 0;
   float judge = 0.01f;  // relative L2 tolerance of the closure against the regularized f1
   size_t off_params = 0, off_m = 0, off_v = 0, off_grads = 0, off_w = 0, off_bias = 0, off_stdz = 0,
-         off_fb = 0, off_save = 0, off_dyt = 0, off_dz1 = 0, off_dz2 = 0, off_partial = 0, off_loss = 0;
+         off_fb = 0, off_save = 0, off_dyt = 0, off_dz1 = 0, off_dz2 = 0, off_partial = 0, off_loss = 0,
+         off_gpartial = 0;
   char *ws = nullptr;
   MlpBuffers B{};
 };
@@ -109,6 +110,14 @@ struct lbm_grid {
   BlockLevel single;              // dense / block-sparse
   std::vector<MultiresLevel> mr;  // multires
   std::vector<LevelRT> lv;
+  // launch lists of one step, one per buffer-role state met so far (roles
+  // cycle with a period of at most 6 steps); cleared when the collision, the
+  // closure or the merge limit changes
+  struct StepPlan {
+    std::vector<int32_t> roles_in, roles_out;  // (cur, prev, nxt) of every level
+    std::vector<Launch> launches;
+  };
+  std::vector<StepPlan> plans;
   size_t off_partial = 0, off_mid = 0, off_check = 0, total = 0;
   int64_t partial_rows = 0;
   char *ws = nullptr;
@@ -222,6 +231,21 @@ void level_update(const lbm_grid *g, const std::vector<LevelRT> &lv, int l, int 
     push(kKernelLevelMerged, fused, 0, nb);
     for (int k = 0; k < 4; ++k) out.back().gcount[k] = (int32_t)gc[k];
   };
+  if (g->desc.schedule == LBM_DISAGG_UNIFORM_FUSED && l > 0) {
+    // the paper's schedule: uniform groups fused, the jump group streamed
+    // (gathers stored) and then collided in place; the groups are
+    // independent, so the jump collision may follow the uniform kernels
+    if (merge) {
+      push_merged(2);
+    } else {
+      push(kKernelFull, 1, first[3], (int32_t)gc[3]);
+      push(kKernelMasked, 1, first[2], (int32_t)gc[2]);
+      push(kKernelBoundary, 1, first[1], (int32_t)gc[1]);
+      push(kKernelJump, 0, first[0], (int32_t)gc[0]);
+    }
+    push(kKernelCollide, 1, first[0], (int32_t)gc[0]);
+    return;
+  }
   if (plain && l > 0) {
     // unfused baseline: streaming kernels, then collision in place
     if (merge) {
@@ -269,10 +293,51 @@ void level_schedule(const lbm_grid *g, std::vector<LevelRT> &lv, int l, int subs
   rotate(lv[l]);
 }
 
+// Buffers a launch reads and writes (for the independence test below).
+void launch_buffers(const Launch &x, std::vector<const void *> &rd, std::vector<const void *> &wr) {
+  rd.assign({x.args.src});
+  if (x.kind == kKernelJump || x.kind == kKernelLevelMerged)
+    for (int t = 0; t < 5; ++t) rd.push_back(x.mr.src[t]);
+  wr.assign({x.args.dst});
+}
+
+bool disjoint(const std::vector<const void *> &a, const std::vector<const void *> &b) {
+  for (const void *p : a)
+    for (const void *q : b)
+      if (p == q) return false;
+  return true;
+}
+
 // Launches of one (coarse) step; lv is advanced to the state after it.
+// Consecutive fused merged level updates that share no buffer between one's
+// writes and the other's reads or writes run as one launch (on a 3-level
+// grid of small levels: 7 level updates in 4 launches).
 void step_launches(const lbm_grid *g, std::vector<LevelRT> &lv, std::vector<Launch> &out) {
+  std::vector<Launch> seq;
+  level_schedule(g, lv, (int)lv.size() - 1, 0, seq);
   out.clear();
-  level_schedule(g, lv, (int)lv.size() - 1, 0, out);
+  std::vector<const void *> r0, w0, r1, w1;
+  for (size_t k = 0; k < seq.size(); ++k) {
+    const Launch &a = seq[k];
+    if (k + 1 < seq.size() && a.kind == kKernelLevelMerged && a.fused == 1 &&
+        seq[k + 1].kind == kKernelLevelMerged && seq[k + 1].fused == 1) {
+      const Launch &b = seq[k + 1];
+      launch_buffers(a, r0, w0);
+      launch_buffers(b, r1, w1);
+      if (disjoint(w0, r1) && disjoint(w0, w1) && disjoint(w1, r0)) {
+        Launch x = a;
+        x.kind = kKernelLevelPair;
+        x.count = a.count + b.count;
+        for (int t = 0; t < 4; ++t) x.gcount2[t] = b.gcount[t];
+        x.args2 = b.args;
+        x.mr2 = b.mr;
+        out.push_back(x);
+        ++k;
+        continue;
+      }
+    }
+    out.push_back(a);
+  }
 }
 
 SlotArgs slot_args(const lbm_grid *g, const LevelRT &r) {
@@ -297,6 +362,56 @@ int32_t coll_code(const lbm_grid *g) {
   return g->collision == LBM_MLP ? 2 : (g->collision == LBM_REGULARIZED ? 1 : 0);
 }
 
+std::vector<int32_t> roles_of(const std::vector<LevelRT> &lv) {
+  std::vector<int32_t> r;
+  r.reserve(3 * lv.size());
+  for (const LevelRT &x : lv) {
+    r.push_back(x.cur);
+    r.push_back(x.prev);
+    r.push_back(x.nxt);
+  }
+  return r;
+}
+
+// The launch plan of the next step from the grid's current buffer roles,
+// built (from a copy of the level state) the first time those roles occur.
+const lbm_grid::StepPlan &step_plan(lbm_grid *g) {
+  const std::vector<int32_t> key = roles_of(g->lv);
+  for (const auto &p : g->plans)
+    if (p.roles_in == key) return p;
+  lbm_grid::StepPlan p;
+  p.roles_in = key;
+  std::vector<LevelRT> next = g->lv;
+  step_launches(g, next, p.launches);
+  p.roles_out = roles_of(next);
+  g->plans.push_back(std::move(p));
+  return g->plans.back();
+}
+
+// The closure's GELU, 0.5 x (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))), as
+// kGeluSegs linear pieces over [-8, 8): piece j on [x0, x0 + h] is the
+// chord through its end points lowered by the mean of the largest and
+// smallest deviation of the function from the chord (sampled), which
+// halves the worst error.  (slope, intercept) per piece, FP64 -> FP32.
+std::vector<float> gelu_table() {
+  auto gelu = [](double x) { return 0.5 * x * (1.0 + std::tanh(0.7978845608028654 * (x + 0.044715 * x * x * x))); };
+  std::vector<float> t(2 * kGeluSegs);
+  const double h = 1.0 / kGeluPerUnit;
+  for (int j = 0; j < kGeluSegs; ++j) {
+    const double x0 = -8.0 + j * h, x1 = x0 + h;
+    const double a = (gelu(x1) - gelu(x0)) / h, b = gelu(x0) - a * x0;
+    double dmin = 0.0, dmax = 0.0;
+    for (int k = 1; k < 64; ++k) {
+      const double x = x0 + h * k / 64.0, d = gelu(x) - (a * x + b);
+      dmin = std::min(dmin, d);
+      dmax = std::max(dmax, d);
+    }
+    t[2 * j] = (float)a;
+    t[2 * j + 1] = (float)(b + 0.5 * (dmin + dmax));
+  }
+  return t;
+}
+
 }  // namespace
 
 extern "C" {
@@ -312,10 +427,13 @@ lbm_status lbm_grid_create(const lbm_grid_desc *d, lbm_grid **out) {
   if (d->collision < LBM_BGK || d->collision > LBM_MLP) return fail(LBM_ERR_INVALID_ARG, "unknown collision");
   if (d->collision == LBM_MLP)
     return fail(LBM_ERR_UNSUPPORTED, "the MLP closure is selected with lbm_set_collision");
-  if (d->schedule != LBM_PLAIN_SINGLE_KERNEL && d->schedule != LBM_DISAGG && d->schedule != LBM_DISAGG_BITMASK)
+  if (d->schedule != LBM_PLAIN_SINGLE_KERNEL && d->schedule != LBM_DISAGG && d->schedule != LBM_DISAGG_BITMASK &&
+      d->schedule != LBM_DISAGG_UNIFORM_FUSED)
     return fail(LBM_ERR_INVALID_ARG, "unknown schedule");
   if (d->schedule == LBM_DISAGG_BITMASK && d->kind == LBM_MULTIRES)
     return fail(LBM_ERR_UNSUPPORTED, "bitmask-based grouping is built for dense and block-sparse grids");
+  if (d->schedule == LBM_DISAGG_UNIFORM_FUSED && d->kind != LBM_MULTIRES)
+    return fail(LBM_ERR_INVALID_ARG, "LBM_DISAGG_UNIFORM_FUSED is a multires schedule");
   if (d->lattice != 0 && d->lattice != 19 && d->lattice != 27)
     return fail(LBM_ERR_INVALID_ARG, "lattice must be 19 or 27");
   if (d->lattice == 27 && d->kind == LBM_MULTIRES)
@@ -553,18 +671,18 @@ lbm_status lbm_step(lbm_grid *g, int32_t n, void *stream) {
   if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
   if (n < 0) return fail(LBM_ERR_INVALID_ARG, "negative step count");
-  std::vector<Launch> launches;
+  const float judge = g->mlp ? g->mlp->judge : 0.0f;  // may change between steps
   for (int32_t k = 0; k < n; ++k) {
-    std::vector<LevelRT> next = g->lv;
-    step_launches(g, next, launches);
-    for (const Launch &x : launches) {
+    const lbm_grid::StepPlan &p = step_plan(g);
+    for (Launch x : p.launches) {
+      x.args.mlp_judge = judge;
       hipError_t e = g->ops.one(x, g->desc.storage, coll_code(g), (hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "step launch");
     }
     for (size_t l = 0; l < g->lv.size(); ++l) {
-      g->lv[l].cur = next[l].cur;
-      g->lv[l].prev = next[l].prev;
-      g->lv[l].nxt = next[l].nxt;
+      g->lv[l].cur = p.roles_out[3 * l];
+      g->lv[l].prev = p.roles_out[3 * l + 1];
+      g->lv[l].nxt = p.roles_out[3 * l + 2];
     }
   }
   return LBM_OK;
@@ -736,7 +854,7 @@ lbm_status lbm_mlp_create(lbm_mlp **out, size_t *bytes) {
   take(m->off_m, kMlpParams * 4);
   take(m->off_v, kMlpParams * 4);
   take(m->off_grads, kMlpParams * 4);
-  take(m->off_w, kWPackedElems * 2);
+  take(m->off_w, kWPackedElems * 2 + kGeluTabBytes);  // packed weights, then the GELU table
   take(m->off_bias, kBiasFloats * 4);
   take(m->off_stdz, kStdFloats * 4);
   take(m->off_fb, 256);
@@ -745,6 +863,7 @@ lbm_status lbm_mlp_create(lbm_mlp **out, size_t *bytes) {
   take(m->off_dz1, (size_t)bmax * 64 * 4);
   take(m->off_dz2, (size_t)bmax * 64 * 4);
   take(m->off_partial, 8192 * 8);
+  take(m->off_gpartial, (size_t)((bmax + 127) / 128) * kMlpParams * 4);
   take(m->off_loss, 64);
   m->total = off;
   m->B.batch_max = bmax;
@@ -773,6 +892,7 @@ lbm_status lbm_mlp_bind(lbm_mlp *m, void *dev, size_t bytes, void *stream) {
   B.dz1 = (float *)(m->ws + m->off_dz1);
   B.dz2 = (float *)(m->ws + m->off_dz2);
   B.partial = (double *)(m->ws + m->off_partial);
+  B.gpartial = (float *)(m->ws + m->off_gpartial);
   hipStream_t s = (hipStream_t)stream;
   std::vector<float> zeros(kMlpParams, 0.0f), stdz(kStdFloats, 0.0f);
   for (int i = 0; i < 32; ++i) {
@@ -785,6 +905,9 @@ lbm_status lbm_mlp_bind(lbm_mlp *m, void *dev, size_t bytes, void *stream) {
   if (!e) e = hipMemcpyAsync(B.adam_v, zeros.data(), kMlpParams * 4, hipMemcpyHostToDevice, s);
   if (!e) e = hipMemcpyAsync(B.stdz, stdz.data(), kStdFloats * 4, hipMemcpyHostToDevice, s);
   if (!e) e = hipMemcpyAsync(B.fallbacks, zero_count, sizeof zero_count, hipMemcpyHostToDevice, s);
+  const std::vector<float> gtab = gelu_table();
+  if (!e) e = hipMemcpyAsync(m->ws + m->off_w + kWPackedElems * 2, gtab.data(), kGeluTabBytes,
+                             hipMemcpyHostToDevice, s);
   if (!e) e = mlp_pack(B, s);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(e, "mlp_bind");
@@ -868,8 +991,25 @@ lbm_status lbm_mlp_train_step(lbm_mlp *m, const float *f, const int64_t *idx, in
   if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = mlp_gradients(m->B, f, idx, n, loss, s);
-  if (!e) e = mlp_adam(m->B, lr, t, s);
+  if (!e) e = mlp_adam(m->B, m->B.grads, lr, t, s);
   if (e) return hip_fail(e, "mlp_train_step");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_adam(lbm_mlp *m, const float *grads, float lr, int32_t t, void *stream) {
+  if (!m || !grads) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (t < 1 || !(lr > 0)) return fail(LBM_ERR_INVALID_ARG, "need t >= 1 and lr > 0");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipError_t e = mlp_adam(m->B, grads, lr, t, (hipStream_t)stream);
+  if (e) return hip_fail(e, "mlp_adam");
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_init_params(lbm_mlp *m, uint64_t seed, void *stream) {
+  if (!m) return fail(LBM_ERR_INVALID_ARG, "null argument");
+  if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
+  hipError_t e = mlp_init(m->B, seed, (hipStream_t)stream);
+  if (e) return hip_fail(e, "mlp_init_params");
   return LBM_OK;
 }
 
@@ -912,6 +1052,7 @@ lbm_status lbm_set_collision(lbm_grid *g, lbm_collision c, const lbm_mlp *m) {
     g->mlp = m;
   }
   g->collision = c;
+  g->plans.clear();
   return LBM_OK;
 }
 
@@ -919,6 +1060,7 @@ lbm_status lbm_set_merge_limit(lbm_grid *g, int64_t max_blocks) {
   if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
   if (max_blocks < 0) return fail(LBM_ERR_INVALID_ARG, "the merge limit must be >= 0");
   g->merge_max = max_blocks;
+  g->plans.clear();
   return LBM_OK;
 }
 

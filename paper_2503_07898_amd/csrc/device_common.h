@@ -218,6 +218,41 @@ __device__ __forceinline__ void hermite2(float pxx, float pyy, float pzz, float 
 #endif
 }
 
+#ifndef LBM_Q27
+// Non-equilibrium stress Pi = sum_i c_i c_i (h_i - h^eq_i) of a D3Q19
+// voxel as (xx, yy, zz, xy, xz, yz).
+__device__ __forceinline__ void neq_stress(const float (&h)[Q], const Moments &m, float (&p)[6]) {
+  const float p78 = h[7] + h[8], p910 = h[9] + h[10], p1112 = h[11] + h[12];
+  const float p1314 = h[13] + h[14], p1516 = h[15] + h[16], p1718 = h[17] + h[18];
+  const float sxx = (h[1] + h[2]) + p78 + p910 + p1112 + p1314;
+  const float syy = (h[3] + h[4]) + p78 + p910 + p1516 + p1718;
+  const float szz = (h[5] + h[6]) + p1112 + p1314 + p1516 + p1718;
+  const float d3 = m.drho * (1.0f / 3.0f);
+  p[0] = sxx - d3 - m.rho * m.ux * m.ux;
+  p[1] = syy - d3 - m.rho * m.uy * m.uy;
+  p[2] = szz - d3 - m.rho * m.uz * m.uz;
+  p[3] = (p78 - p910) - m.rho * m.ux * m.uy;
+  p[4] = (p1112 - p1314) - m.rho * m.ux * m.uz;
+  p[5] = (p1516 - p1718) - m.rho * m.uy * m.uz;
+}
+
+// Squared Euclidean norm of the D3Q19 Hermite vector hermite2(P), summed in
+// closed form over the lattice: the rest population gives (1.5 t)^2 with
+// t = tr P / 3, each axis pair 2 (P_aa - t)^2 / 16, each edge plane ab
+// 2 ((e + 2 P_ab)^2 + (e - 2 P_ab)^2) / 64 with e = P_aa + P_bb - t.
+__device__ __forceinline__ float hermite2_norm2(float pxx, float pyy, float pzz, float pxy, float pxz,
+                                                float pyz) {
+  const float t = (pxx + pyy + pzz) * (1.0f / 3.0f);
+  const float ax = pxx - t, ay = pyy - t, az = pzz - t;
+  const float exy = pxx + pyy - t, exz = pxx + pzz - t, eyz = pyy + pzz - t;
+  float s = 2.25f * (t * t);
+  s = fmaf(0.125f, ax * ax + ay * ay + az * az, s);
+  s = fmaf(0.0625f, exy * exy + exz * exz + eyz * eyz, s);
+  s = fmaf(0.25f, pxy * pxy + pxz * pxz + pyz * pyz, s);
+  return s;
+}
+#endif
+
 __device__ __forceinline__ void f1_projection(const float (&h)[Q], const Moments &m, float (&f1)[Q]) {
 #ifdef LBM_Q27
   // second moments of h over opposite pairs (c c is even in c)
@@ -239,19 +274,9 @@ __device__ __forceinline__ void f1_projection(const float (&h)[Q], const Moments
   hermite2(sxx - d3 - m.rho * m.ux * m.ux, syy - d3 - m.rho * m.uy * m.uy, szz - d3 - m.rho * m.uz * m.uz,
            sxy - m.rho * m.ux * m.uy, sxz - m.rho * m.ux * m.uz, syz - m.rho * m.uy * m.uz, f1);
 #else
-  const float p78 = h[7] + h[8], p910 = h[9] + h[10], p1112 = h[11] + h[12];
-  const float p1314 = h[13] + h[14], p1516 = h[15] + h[16], p1718 = h[17] + h[18];
-  const float sxx = (h[1] + h[2]) + p78 + p910 + p1112 + p1314;
-  const float syy = (h[3] + h[4]) + p78 + p910 + p1516 + p1718;
-  const float szz = (h[5] + h[6]) + p1112 + p1314 + p1516 + p1718;
-  const float d3 = m.drho * (1.0f / 3.0f);
-  const float pxx = sxx - d3 - m.rho * m.ux * m.ux;
-  const float pyy = syy - d3 - m.rho * m.uy * m.uy;
-  const float pzz = szz - d3 - m.rho * m.uz * m.uz;
-  const float pxy = (p78 - p910) - m.rho * m.ux * m.uy;
-  const float pxz = (p1112 - p1314) - m.rho * m.ux * m.uz;
-  const float pyz = (p1516 - p1718) - m.rho * m.uy * m.uz;
-  hermite2(pxx, pyy, pzz, pxy, pxz, pyz, f1);
+  float p[6];
+  neq_stress(h, m, p);
+  hermite2(p[0], p[1], p[2], p[3], p[4], p[5], f1);
 #endif
 }
 

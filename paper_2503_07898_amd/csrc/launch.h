@@ -50,7 +50,8 @@ enum KernelKind : int32_t {
   kKernelLex = 6,           // dense lexicographic single kernel
   kKernelInteriorBits = 7,  // bitmask grouping: all blocks, non-boundary ones processed
   kKernelBoundaryBits = 8,  // bitmask grouping: all blocks, boundary ones processed
-  kKernelLevelMerged = 9    // every group of a small multires level in one launch
+  kKernelLevelMerged = 9,   // every group of a small multires level in one launch
+  kKernelLevelPair = 10      // two independent merged level updates (fused) in one launch
 };
 
 // Sources of the multires jump gather, indexed by table tag: own level now,
@@ -65,11 +66,16 @@ struct MrArgs {
 
 struct Launch {
   int32_t kind;
-  int32_t fused;          // 0: store the gathered (pre-collision) populations only
+  int32_t fused;          // 0: store the gathered (pre-collision) populations only; 2 (merged
+                          // level launch): uniform groups fused, jump group stored only
   int32_t first, count;   // block range of the launch
   int32_t gcount[4];      // kKernelLevelMerged: blocks of the jump, boundary, masked, full groups
   StepArgs args;
   MrArgs mr;
+  // kKernelLevelPair: the second level update (its group counts, arguments)
+  int32_t gcount2[4];
+  StepArgs args2;
+  MrArgs mr2;
 };
 
 // ---- learned closure: training and utility launches (mlp_kernels.hip) ----
@@ -87,6 +93,7 @@ struct MlpBuffers {
   float *dz1;         // [batch_max][64]
   float *dz2;         // [batch_max][64]
   double *partial;    // reduction partials
+  float *gpartial;    // [batch_max / 128][kMlpParams] per-chunk weight gradients
   int64_t batch_max;
 };
 
@@ -96,7 +103,10 @@ hipError_t mlp_fit_standardization(const MlpBuffers &B, const float *f, int64_t 
 hipError_t mlp_forward(const MlpBuffers &B, const float *f, int64_t n, float *y, hipStream_t s);
 hipError_t mlp_gradients(const MlpBuffers &B, const float *f, const int64_t *idx, int64_t n, double *loss,
                          hipStream_t s);
-hipError_t mlp_adam(const MlpBuffers &B, float lr, int32_t t, hipStream_t s);
+// Adam step t on `grads` (B.grads or a caller's array), then the bf16 copy
+hipError_t mlp_adam(const MlpBuffers &B, const float *grads, float lr, int32_t t, hipStream_t s);
+// seeded He-uniform weights and zero biases, then the bf16 copy
+hipError_t mlp_init(const MlpBuffers &B, uint64_t seed, hipStream_t s);
 hipError_t launch_sample_pre(const StepArgs &a, int32_t storage, int32_t b0, int32_t nb, uint64_t seed, int64_t n,
                              float *out, hipStream_t s);
 }  // namespace k19

@@ -37,6 +37,13 @@ constexpr int kW1Elems = (kMlpInPad / 16) * (kMlpHidden / 32) * 64 * 8;   // 204
 constexpr int kW2Elems = (kMlpHidden / 16) * (kMlpHidden / 32) * 64 * 8;  // 4096
 constexpr int kW3Elems = (kMlpHidden / 16) * (kMlpOutPad / 32) * 64 * 8;  // 2048
 constexpr int kWPackedElems = kW1Elems + kW2Elems + kW3Elems;            // 8192 bf16 = 16 KB
+// GELU as a table of linear pieces: kGeluSegs segments of width
+// 1/kGeluPerUnit over [-8, 8), each (slope, intercept) as two floats; the
+// table follows the packed weights in device memory and in LDS.
+constexpr int kGeluPerUnit = 32;
+constexpr int kGeluSegs = 16 * kGeluPerUnit;                       // 512
+constexpr int kGeluTabBytes = kGeluSegs * 8;                       // 4 KB
+constexpr int kWStageElems = kWPackedElems + kGeluTabBytes / 2;    // weights + table, in bf16 units
 constexpr int kBiasFloats = kMlpHidden + kMlpHidden + kMlpOutPad;          // 160
 constexpr int kStdFloats = 4 * 32;  // in_mean, in_inv_std, out_std, out_mean (19 used of 32)
 
@@ -77,6 +84,18 @@ __device__ __forceinline__ float gelu_f(float x) {
   constexpr float c2 = 0.044715f * c1;
   const float e = __builtin_amdgcn_exp2f(x * fmaf(c2, x * x, c1));
   return x * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// tanh-form GELU from the table of linear pieces in LDS (tab: the
+// (slope, intercept) pairs; the pieces interpolate the function with their
+// error centred, at most 5e-5 away from it, below the bf16 rounding of the
+// result).  Arguments beyond [-8, 8) use the outermost piece: 0 below, x
+// above.
+__device__ __forceinline__ float gelu_tab(float x, const float2 *tab) {
+  const float t = __builtin_amdgcn_fmed3f(fmaf(x, (float)kGeluPerUnit, 8.0f * kGeluPerUnit), 0.0f,
+                                          (float)(kGeluSegs - 1));
+  const float2 c = tab[(int)t];
+  return fmaf(c.x, x, c.y);
 }
 
 // derivative of gelu_f
@@ -127,7 +146,7 @@ __device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMI
 
 // GELU of hidden accumulators, written back as the next layer's bf16
 // activations (and, when training, z and h to `save`).
-__device__ __forceinline__ void hidden_out(__bf16 *act, const f32x16_t (&acc)[2][2], int lane,
+__device__ __forceinline__ void hidden_out(__bf16 *act, const f32x16_t (&acc)[2][2], const float2 *gtab, int lane,
                                            float *save, int64_t row0, int zoff, int hoff, int64_t nvalid) {
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -137,7 +156,7 @@ __device__ __forceinline__ void hidden_out(__bf16 *act, const f32x16_t (&acc)[2]
       for (int r = 0; r < 16; ++r) {
         const int row = 32 * t + mfma_d_row(lane, r), col = 32 * n + mfma_d_col(lane);
         const float z = acc[t][n][r];
-        const __bf16 hb = (__bf16)gelu_f(z);
+        const __bf16 hb = (__bf16)gelu_tab(z, gtab);
         act[row * kActStride + col] = hb;
         if (save && row0 + row < nvalid) {
           save[(row0 + row) * kSaveFloats + zoff + col] = z;
@@ -165,11 +184,12 @@ __device__ __forceinline__ void mlp_forward_wave(const float (&x)[Q], float (&yt
   f32x16_t h[2][2];
   mfma_layer<kMlpInPad, kMlpHidden>(act, wl, bias, h, lane);
   wave_lds_sync();
-  hidden_out(act, h, lane, save, row0, kSaveZ1, kSaveH1, nvalid);
+  const float2 *gtab = (const float2 *)(wl + kWPackedElems);
+  hidden_out(act, h, gtab, lane, save, row0, kSaveZ1, kSaveH1, nvalid);
   wave_lds_sync();
   mfma_layer<kMlpHidden, kMlpHidden>(act, wl + kW1Elems, bias + kMlpHidden, h, lane);
   wave_lds_sync();
-  hidden_out(act, h, lane, save, row0, kSaveZ2, kSaveH2, nvalid);
+  hidden_out(act, h, gtab, lane, save, row0, kSaveZ2, kSaveH2, nvalid);
   wave_lds_sync();
   f32x16_t o[2][1];
   mfma_layer<kMlpHidden, kMlpOutPad>(act, wl + kW1Elems + kW2Elems, bias + 2 * kMlpHidden, o, lane);
@@ -224,16 +244,16 @@ __device__ __forceinline__ void bias_init(f32x16_t &acc, const float *bias, int 
 
 // B operands (two voxel tiles) of one 16-feature chunk c of a hidden layer
 // from the GELU'd accumulators of feature tile c/2.
-__device__ __forceinline__ void hidden_chunk(const f32x16_t &z0, const f32x16_t &z1, int c, bf16x8_t &b0,
-                                             bf16x8_t &b1) {
+__device__ __forceinline__ void hidden_chunk(const f32x16_t &z0, const f32x16_t &z1, int c, const float2 *gtab,
+                                             bf16x8_t &b0, bf16x8_t &b1) {
   const int r0 = 8 * (c & 1);
   uint32_t x[2][2], y[2][2];  // [tile][dword]
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    x[0][k] = pack_bf16(gelu_f(z0[r0 + 2 * k]), gelu_f(z0[r0 + 2 * k + 1]));
-    y[0][k] = pack_bf16(gelu_f(z0[r0 + 4 + 2 * k]), gelu_f(z0[r0 + 4 + 2 * k + 1]));
-    x[1][k] = pack_bf16(gelu_f(z1[r0 + 2 * k]), gelu_f(z1[r0 + 2 * k + 1]));
-    y[1][k] = pack_bf16(gelu_f(z1[r0 + 4 + 2 * k]), gelu_f(z1[r0 + 4 + 2 * k + 1]));
+    x[0][k] = pack_bf16(gelu_tab(z0[r0 + 2 * k], gtab), gelu_tab(z0[r0 + 2 * k + 1], gtab));
+    y[0][k] = pack_bf16(gelu_tab(z0[r0 + 4 + 2 * k], gtab), gelu_tab(z0[r0 + 4 + 2 * k + 1], gtab));
+    x[1][k] = pack_bf16(gelu_tab(z1[r0 + 2 * k], gtab), gelu_tab(z1[r0 + 2 * k + 1], gtab));
+    y[1][k] = pack_bf16(gelu_tab(z1[r0 + 4 + 2 * k], gtab), gelu_tab(z1[r0 + 4 + 2 * k + 1], gtab));
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -265,6 +285,7 @@ __device__ __forceinline__ void layer_tile(const __bf16 *wl, const float *bias, 
 // in LDS (wl), biases b1|b2|b3 in global memory.
 __device__ __forceinline__ void mlp_forward_wave_reg(const float (&x)[Q], float (&yt)[Q], const __bf16 *wl,
                                                      const float *bias, int lane) {
+  const float2 *gtab = (const float2 *)(wl + kWPackedElems);
   // layer 1 operands: chunk c holds features 16c..16c+15; the lane's own
   // features 16c..16c+7 (F0) and 16c+8..16c+15 (F1) are swapped across
   // halves so that F0-slot registers form tile 0 and F1-slot registers tile 1
@@ -291,15 +312,15 @@ __device__ __forceinline__ void mlp_forward_wave_reg(const float (&x)[Q], float 
   for (int m = 0; m < 2; ++m) {
     f32x16_t z[2];
     layer_tile<2, 2>(wl, bias, b1, m, z, lane);
-    hidden_chunk(z[0], z[1], 2 * m, b2[2 * m][0], b2[2 * m][1]);
-    hidden_chunk(z[0], z[1], 2 * m + 1, b2[2 * m + 1][0], b2[2 * m + 1][1]);
+    hidden_chunk(z[0], z[1], 2 * m, gtab, b2[2 * m][0], b2[2 * m][1]);
+    hidden_chunk(z[0], z[1], 2 * m + 1, gtab, b2[2 * m + 1][0], b2[2 * m + 1][1]);
   }
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     f32x16_t z[2];
     layer_tile<4, 2>(wl + kW1Elems, bias + kMlpHidden, b2, m, z, lane);
-    hidden_chunk(z[0], z[1], 2 * m, b3[2 * m][0], b3[2 * m][1]);
-    hidden_chunk(z[0], z[1], 2 * m + 1, b3[2 * m + 1][0], b3[2 * m + 1][1]);
+    hidden_chunk(z[0], z[1], 2 * m, gtab, b3[2 * m][0], b3[2 * m][1]);
+    hidden_chunk(z[0], z[1], 2 * m + 1, gtab, b3[2 * m + 1][0], b3[2 * m + 1][1]);
   }
   f32x16_t o[1][2];
   layer_tile<4, 1>(wl + kW1Elems + kW2Elems, bias + 2 * kMlpHidden, b3, 0, o[0], lane);
@@ -324,31 +345,42 @@ __device__ __forceinline__ void mlp_forward_wave_reg(const float (&x)[Q], float 
   }
 }
 
-// Copies the packed weights (16 KB) from global memory to LDS; every thread
-// of the workgroup must call it before any wave returns.
+// Copies the packed weights and the GELU table (20 KB) from global memory to
+// LDS (wl holds kWStageElems); every thread of the workgroup must call it
+// before any wave returns.
 __device__ __forceinline__ void stage_weights(__bf16 *wl, const __bf16 *wg) {
   const uint4 *src = (const uint4 *)wg;
   uint4 *dst = (uint4 *)wl;
-  for (int k = threadIdx.x; k < kWPackedElems / 8; k += blockDim.x) dst[k] = src[k];
+  for (int k = threadIdx.x; k < kWStageElems / 8; k += blockDim.x) dst[k] = src[k];
   __syncthreads();
 }
 
-// Second-order Hermite projection, P(y)_i = w_i/(2 c_s^4) Q_i : sum_j Q_j y_j:
-// keeps the stress-like part of y and drops mass, momentum and every
-// higher (ghost) moment.
-__device__ __forceinline__ void project_out(float (&y)[Q]) {
+// Q-weighted second moment A = sum_j Q_j y_j (Q_j = c_j c_j - c_s^2 I) as
+// (xx, yy, zz, xy, xz, yz): the coordinates of y's second-order Hermite
+// part, P(y) = hermite2(A).
+__device__ __forceinline__ void q_stress(const float (&y)[Q], float (&a)[6]) {
   float s = y[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i) s = s + y[i];
   const float p78 = y[7] + y[8], p910 = y[9] + y[10], p1112 = y[11] + y[12];
   const float p1314 = y[13] + y[14], p1516 = y[15] + y[16], p1718 = y[17] + y[18];
   const float s3 = s * (1.0f / 3.0f);
-  const float pxx = (y[1] + y[2]) + p78 + p910 + p1112 + p1314 - s3;
-  const float pyy = (y[3] + y[4]) + p78 + p910 + p1516 + p1718 - s3;
-  const float pzz = (y[5] + y[6]) + p1112 + p1314 + p1516 + p1718 - s3;
+  a[0] = (y[1] + y[2]) + p78 + p910 + p1112 + p1314 - s3;
+  a[1] = (y[3] + y[4]) + p78 + p910 + p1516 + p1718 - s3;
+  a[2] = (y[5] + y[6]) + p1112 + p1314 + p1516 + p1718 - s3;
   // the off-diagonal sums pair opposite directions (c_a c_b is even in c)
-  const float pxy = p78 - p910, pxz = p1112 - p1314, pyz = p1516 - p1718;
-  hermite2(pxx, pyy, pzz, pxy, pxz, pyz, y);
+  a[3] = p78 - p910;
+  a[4] = p1112 - p1314;
+  a[5] = p1516 - p1718;
+}
+
+// Second-order Hermite projection, P(y)_i = w_i/(2 c_s^4) Q_i : sum_j Q_j y_j:
+// keeps the stress-like part of y and drops mass, momentum and every
+// higher (ghost) moment.
+__device__ __forceinline__ void project_out(float (&y)[Q]) {
+  float a[6];
+  q_stress(y, a);
+  hermite2(a[0], a[1], a[2], a[3], a[4], a[5], y);
 }
 
 }  // inline namespace

@@ -6,9 +6,13 @@
 //                 projection, squared error against the regularized target
 //                 f1/rho, and the loss gradient with respect to the raw
 //                 outputs (dyt); intermediates go to `save`;
-//   k_mlp_bwd     per sample: back through layers 3 and 2 (dz2, dz1) with the
-//                 bf16 weights the forward used;
-//   k_mlp_wgrad   per parameter: sums over the batch in a fixed order;
+//   k_mlp_bwd_mfma    per wave of 64 samples: back through layers 3 and 2
+//                 (dz2, dz1) on the matrix cores with the bf16 weights the
+//                 forward used;
+//   k_mlp_wgrad_mfma  per chunk of 128 samples: weight gradients on the
+//                 matrix cores, bias gradients as column sums, one partial
+//                 gradient per chunk;
+//   k_mlp_grad_final  per parameter: the chunk partials summed in order;
 //   k_mlp_adam    per parameter: Adam on the FP32 master weights;
 //   k_mlp_pack    master weights -> bf16 operand-order copy + biases.
 // Everything is deterministic (fixed summation orders, no atomics).
@@ -62,7 +66,7 @@ __device__ __forceinline__ Moments closure_inputs(const float (&h)[Q], const flo
 __global__ __launch_bounds__(256) void k_mlp_fwd(const float *f, const int64_t *idx, int64_t n, const __bf16 *wg,
                                                  const float *bias, const float *stdz, float *save,
                                                  float *dyt, float *yout, double *partial) {
-  __shared__ __attribute__((aligned(16))) __bf16 wl[kWPackedElems];
+  __shared__ __attribute__((aligned(16))) __bf16 wl[kWStageElems];
   __shared__ __attribute__((aligned(16))) __bf16 act[4][64 * kActStride];
   stage_weights(wl, wg);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -116,61 +120,187 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *f, const int64_t *
   if (lane == 0 && partial) partial[blockIdx.x * 4 + wave] = e;
 }
 
-// ------------------------------------------------------- hidden backward --
-// W2 and W3 as the forward used them (rounded to bf16), from the masters.
-__global__ __launch_bounds__(256) void k_mlp_bwd(int64_t n, const float *params, const float *save,
-                                                 const float *dyt, float *dz1, float *dz2) {
-  __shared__ float w2[64 * 64], w3[64 * 19];
-  for (int k = threadIdx.x; k < 64 * 64; k += blockDim.x) w2[k] = bf16_value(params[kMlpW2 + k]);
-  for (int k = threadIdx.x; k < 64 * 19; k += blockDim.x) w3[k] = bf16_value(params[kMlpW3 + k]);
-  __syncthreads();
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const float *sv = save + s * kSaveFloats;
-  float g[Q];
-#pragma unroll
-  for (int j = 0; j < Q; ++j) g[j] = dyt[s * Q + j];
-  float d2[64];
-  for (int a = 0; a < 64; ++a) {
-    float acc = 0.0f;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) acc = fmaf(g[j], w3[a * 19 + j], acc);
-    const float z = sv[kSaveZ2 + a];
-    d2[a] = acc * gelu_grad_f(z);
-    dz2[s * 64 + a] = d2[a];
-  }
-  for (int a = 0; a < 64; ++a) {
-    float acc = 0.0f;
-    for (int b = 0; b < 64; ++b) acc = fmaf(d2[b], w2[a * 64 + b], acc);
-    dz1[s * 64 + a] = acc * gelu_grad_f(sv[kSaveZ1 + a]);
+// ---------------------------------------------- matrix-core backward pass --
+// Products C[m][n] = sum_k A[m][k] B[n][k] of bf16 operands held in LDS as
+// rows (A: [M][lda], B: [N][ldb], k contiguous, FP32 accumulation) on
+// v_mfma_f32_32x32x16_bf16: lane l loads A row m0 + l%32 and B row
+// n0 + l%32, eight k values each from k0 + 8 (l/32); element r of the
+// result tile is C[m0 + 8(r/4) + 4(l/32) + r%4][n0 + l%32].
+__device__ __forceinline__ void mfma_nt(const __bf16 *A, int lda, int m0, const __bf16 *B, int ldb, int n0, int K,
+                                        f32x16_t &acc, int lane) {
+  const __bf16 *pa = A + (m0 + (lane & 31)) * lda + 8 * (lane >> 5);
+  const __bf16 *pb = B + (n0 + (lane & 31)) * ldb + 8 * (lane >> 5);
+  for (int k = 0; k < K; k += 16) {
+    const bf16x8_t a = *(const bf16x8_t *)(pa + k);
+    const bf16x8_t b = *(const bf16x8_t *)(pb + k);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
 }
 
-// --------------------------------------------------------- weight grads --
-__global__ __launch_bounds__(256) void k_mlp_wgrad(int64_t n, const float *save, const float *dyt,
-                                                   const float *dz1, const float *dz2, float *grads) {
+__device__ __forceinline__ int tile_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+constexpr int kBwdRows = 64;                 // samples per wave
+constexpr int kLd32 = 32 + 8, kLd64 = 64 + 8;  // LDS row strides (bf16), padded against bank conflicts
+
+// Back through layers 3 and 2 for 256 samples per workgroup (64 per wave):
+//   dz2 = (dyt W3^T) o gelu'(z2),  dz1 = (dz2 W2^T) o gelu'(z1),
+// products on the matrix cores with the bf16 weights the forward used and
+// dyt, dz2 rounded to bf16; dz1 and dz2 leave in FP32.
+__global__ __launch_bounds__(256) void k_mlp_bwd_mfma(int64_t n, const float *params, const float *save,
+                                                      const float *dyt, float *dz1, float *dz2) {
+  __shared__ __attribute__((aligned(16))) __bf16 w3[64 * kLd32];   // W3 [a][j]
+  __shared__ __attribute__((aligned(16))) __bf16 w2[64 * kLd64];   // W2 [a][b]
+  __shared__ __attribute__((aligned(16))) __bf16 rows[4][kBwdRows * kLd64];  // per wave: dyt, then dz2
+  for (int k = threadIdx.x; k < 64 * 32; k += blockDim.x) {
+    const int a = k >> 5, j = k & 31;
+    w3[a * kLd32 + j] = (__bf16)(j < Q ? params[kMlpW3 + a * 19 + j] : 0.0f);
+  }
+  for (int k = threadIdx.x; k < 64 * 64; k += blockDim.x) w2[(k >> 6) * kLd64 + (k & 63)] = (__bf16)params[kMlpW2 + k];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * kBwdRows;
+  __bf16 *rw = rows[wave];
+  // this wave's dyt rows [64][32], zero beyond the batch and beyond 19
+  for (int k = lane; k < kBwdRows * 32; k += 64) {
+    const int si = k >> 5, j = k & 31;
+    const int64_t sg = row0 + si;
+    rw[si * kLd32 + j] = (__bf16)(sg < n && j < Q ? dyt[sg * Q + j] : 0.0f);
+  }
+  __syncthreads();
+  // dz2 tiles: samples 32t.., features 32u..
+  f32x16_t acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      acc[t][u] = {};
+      mfma_nt(rw, kLd32, 32 * t, w3, kLd32, 32 * u, 32, acc[t][u], lane);
+    }
+  wave_lds_sync();  // the dyt rows are read; the region now takes dz2
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int si = 32 * t + tile_row(lane, r), a = 32 * u + (lane & 31);
+        const int64_t sg = row0 + si;
+        float d = 0.0f;
+        if (sg < n) {
+          d = acc[t][u][r] * gelu_grad_f(save[sg * kSaveFloats + kSaveZ2 + a]);
+          dz2[sg * 64 + a] = d;
+        }
+        rw[si * kLd64 + a] = (__bf16)d;
+      }
+  wave_lds_sync();
+  // dz1 tiles
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      acc[t][u] = {};
+      mfma_nt(rw, kLd64, 32 * t, w2, kLd64, 32 * u, 64, acc[t][u], lane);
+    }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int si = 32 * t + tile_row(lane, r), a = 32 * u + (lane & 31);
+        const int64_t sg = row0 + si;
+        if (sg < n) dz1[sg * 64 + a] = acc[t][u][r] * gelu_grad_f(save[sg * kSaveFloats + kSaveZ1 + a]);
+      }
+}
+
+constexpr int kWgradChunk = 128;          // samples per workgroup of the weight-gradient pass
+constexpr int kLdS = kWgradChunk + 8;     // LDS row stride (bf16) of transposed operands
+
+// Stages rows [s0, s0 + kWgradChunk) of a [n][ld] FP32 array, columns
+// [c0, c0 + cols) (zero beyond nc valid columns and beyond the batch), into
+// LDS transposed: dst[c][s] in bf16.
+__device__ __forceinline__ void stage_t(__bf16 *dst, int rowsd, const float *src, int ld, int c0, int nc, int64_t s0,
+                                        int64_t n) {
+  for (int k = threadIdx.x; k < rowsd * kWgradChunk; k += blockDim.x) {
+    const int c = k / kWgradChunk, si = k % kWgradChunk;
+    const int64_t sg = s0 + si;
+    dst[c * kLdS + si] = (__bf16)(sg < n && c < nc ? src[sg * ld + c0 + c] : 0.0f);
+  }
+}
+
+// Weight and bias gradients of one chunk of kWgradChunk samples, into
+// partial[chunk][kMlpParams]:
+//   W1[i][a] = sum x_i dz1_a,  W2[a][b] = sum h1_a dz2_b,  W3[a][j] = sum h2_a dyt_j
+// as matrix-core products over the chunk (bf16 operands, FP32 accumulation),
+// biases as FP32 column sums in sample order.
+__global__ __launch_bounds__(256) void k_mlp_wgrad_mfma(int64_t n, const float *save, const float *dyt,
+                                                        const float *dz1, const float *dz2, float *partial) {
+  __shared__ __attribute__((aligned(16))) __bf16 lds[(32 + 64 + 64 + 32) * kLdS];
+  __bf16 *sx = lds, *sd1 = lds + 32 * kLdS, *sh2 = lds + 96 * kLdS, *sdy = lds + 160 * kLdS;
+  const int64_t s0 = (int64_t)blockIdx.x * kWgradChunk;
+  float *out = partial + (size_t)blockIdx.x * kMlpParams;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // phase 1: W1 (waves 0, 1) and W3 (waves 2, 3)
+  stage_t(sx, 32, save, kSaveFloats, kSaveX, Q, s0, n);
+  stage_t(sd1, 64, dz1, 64, 0, 64, s0, n);
+  stage_t(sh2, 64, save, kSaveFloats, kSaveH2, 64, s0, n);
+  stage_t(sdy, 32, dyt, Q, 0, Q, s0, n);
+  __syncthreads();
+  {
+    f32x16_t acc = {};
+    if (wave < 2) {  // W1 tile: inputs 0..31 x features 32 wave..
+      mfma_nt(sx, kLdS, 0, sd1, kLdS, 32 * wave, kWgradChunk, acc, lane);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = tile_row(lane, r), a = 32 * wave + (lane & 31);
+        if (i < Q) out[kMlpW1 + i * 64 + a] = acc[r];
+      }
+    } else {  // W3 tile: features 32 (wave - 2).. x outputs 0..31
+      mfma_nt(sh2, kLdS, 32 * (wave - 2), sdy, kLdS, 0, kWgradChunk, acc, lane);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int a = 32 * (wave - 2) + tile_row(lane, r), j = lane & 31;
+        if (j < Q) out[kMlpW3 + a * 19 + j] = acc[r];
+      }
+    }
+  }
+  // biases: column sums in sample order (FP32)
+  {
+    const int t = threadIdx.x;
+    const int64_t s1 = s0 + kWgradChunk < n ? s0 + kWgradChunk : n;
+    float acc = 0.0f;
+    if (t < 64) {
+      for (int64_t sg = s0; sg < s1; ++sg) acc += dz1[sg * 64 + t];
+      out[kMlpB1 + t] = acc;
+    } else if (t < 128) {
+      for (int64_t sg = s0; sg < s1; ++sg) acc += dz2[sg * 64 + (t - 64)];
+      out[kMlpB2 + t - 64] = acc;
+    } else if (t < 128 + Q) {
+      for (int64_t sg = s0; sg < s1; ++sg) acc += dyt[sg * Q + (t - 128)];
+      out[kMlpB3 + t - 128] = acc;
+    }
+  }
+  __syncthreads();
+  // phase 2: W2 (one 32x32 tile per wave)
+  __bf16 *sh1 = lds, *sd2 = lds + 64 * kLdS;
+  stage_t(sh1, 64, save, kSaveFloats, kSaveH1, 64, s0, n);
+  stage_t(sd2, 64, dz2, 64, 0, 64, s0, n);
+  __syncthreads();
+  f32x16_t acc = {};
+  const int mt = wave >> 1, nt = wave & 1;
+  mfma_nt(sh1, kLdS, 32 * mt, sd2, kLdS, 32 * nt, kWgradChunk, acc, lane);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int a = 32 * mt + tile_row(lane, r), b = 32 * nt + (lane & 31);
+    out[kMlpW2 + a * 64 + b] = acc[r];
+  }
+}
+
+// Sum of the chunk partials in chunk order.
+__global__ void k_mlp_grad_final(const float *partial, int nchunks, float *grads) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kMlpParams) return;
   float acc = 0.0f;
-  if (p < kMlpB1) {  // W1[i][a] = sum x_i dz1_a
-    const int i = p / 64, a = p % 64;
-    for (int64_t s = 0; s < n; ++s) acc = fmaf(save[s * kSaveFloats + kSaveX + i], dz1[s * 64 + a], acc);
-  } else if (p < kMlpW2) {
-    const int a = p - kMlpB1;
-    for (int64_t s = 0; s < n; ++s) acc += dz1[s * 64 + a];
-  } else if (p < kMlpB2) {  // W2[a][b] = sum h1_a dz2_b
-    const int a = (p - kMlpW2) / 64, b = (p - kMlpW2) % 64;
-    for (int64_t s = 0; s < n; ++s) acc = fmaf(save[s * kSaveFloats + kSaveH1 + a], dz2[s * 64 + b], acc);
-  } else if (p < kMlpW3) {
-    const int b = p - kMlpB2;
-    for (int64_t s = 0; s < n; ++s) acc += dz2[s * 64 + b];
-  } else if (p < kMlpB3) {  // W3[a][j] = sum h2_a dyt_j
-    const int a = (p - kMlpW3) / 19, j = (p - kMlpW3) % 19;
-    for (int64_t s = 0; s < n; ++s) acc = fmaf(save[s * kSaveFloats + kSaveH2 + a], dyt[s * Q + j], acc);
-  } else {
-    const int j = p - kMlpB3;
-    for (int64_t s = 0; s < n; ++s) acc += dyt[s * Q + j];
-  }
+  for (int c = 0; c < nchunks; ++c) acc += partial[(size_t)c * kMlpParams + p];
   grads[p] = acc;
 }
 
@@ -192,6 +322,29 @@ __global__ void k_mlp_adam(float *params, const float *grads, float *m, float *v
   m[p] = mm;
   v[p] = vv;
   params[p] -= lr * (mm / b1c) / (sqrtf(vv / b2c) + 1e-8f);
+}
+
+// splitmix64 (Steele, Lea and Flood 2014), a counter-based generator.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// He-uniform initial weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)), zero
+// biases; parameter p draws 53 bits of splitmix64(seed ^ splitmix64(p)).
+__global__ void k_mlp_init(float *params, uint64_t seed) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kMlpParams) return;
+  constexpr double kLim19 = 0.5619514869490163;   // sqrt(6/19)
+  constexpr double kLim64 = 0.30618621784789724;  // sqrt(6/64)
+  double lim = 0.0;
+  if (p < kMlpB1) lim = kLim19;
+  else if ((p >= kMlpW2 && p < kMlpB2) || (p >= kMlpW3 && p < kMlpB3)) lim = kLim64;
+  const uint64_t r = mix64(seed ^ mix64((uint64_t)p));
+  const double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
+  params[p] = (float)((2.0 * u - 1.0) * lim);
 }
 
 // master weights -> packed bf16 operand order and padded biases
@@ -304,17 +457,28 @@ hipError_t mlp_gradients(const MlpBuffers &B, const float *f, const int64_t *idx
   const unsigned nb = (unsigned)waves_blocks(n);
   hipLaunchKernelGGL(k_mlp_fwd, dim3(nb), dim3(256), 0, s, f, idx, n, (const __bf16 *)B.wpacked, B.bias, B.stdz,
                      B.save, B.dyt, (float *)nullptr, B.partial);
-  hipLaunchKernelGGL(k_mlp_bwd, dim3(nb), dim3(256), 0, s, n, B.params, B.save, B.dyt, B.dz1, B.dz2);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, n, B.save, B.dyt, B.dz1,
-                     B.dz2, B.grads);
+  hipLaunchKernelGGL(k_mlp_bwd_mfma, dim3(nb), dim3(256), 0, s, n, B.params, B.save, B.dyt, B.dz1, B.dz2);
+  const int nchunks = (int)((n + kWgradChunk - 1) / kWgradChunk);
+  hipLaunchKernelGGL(k_mlp_wgrad_mfma, dim3(nchunks), dim3(256), 0, s, n, B.save, B.dyt, B.dz1, B.dz2, B.gpartial);
+  hipLaunchKernelGGL(k_mlp_grad_final, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, B.gpartial, nchunks,
+                     B.grads);
   if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, B.partial, (int64_t)nb * 4, n, loss);
   return hipGetLastError();
 }
 
-hipError_t mlp_adam(const MlpBuffers &B, float lr, int32_t t, hipStream_t s) {
+hipError_t mlp_adam(const MlpBuffers &B, const float *grads, float lr, int32_t t, hipStream_t s) {
   const float b1c = 1.0f - powf(0.9f, (float)t), b2c = 1.0f - powf(0.999f, (float)t);
-  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, B.params, B.grads, B.adam_m,
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, B.params, grads, B.adam_m,
                      B.adam_v, lr, b1c, b2c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return mlp_pack(B, s);
+}
+
+hipError_t mlp_init(const MlpBuffers &B, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_init, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, B.params, seed);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   return mlp_pack(B, s);
 }
 

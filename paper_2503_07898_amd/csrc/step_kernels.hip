@@ -128,12 +128,15 @@ __global__ __launch_bounds__(256) void k_block_interior_bits(StepArgs a, int32_t
 // to zero mass and momentum, and falls back per voxel to the regularized
 // operator when a standardized input leaves [-8, 8], a population turns
 // negative, or the closure's non-equilibrium part strays more than the
-// judge tolerance from the regularized operator's.  The packed weights are
-// staged in LDS once per workgroup.
+// judge tolerance from the regularized operator's.  The packed weights and
+// the GELU table are staged in LDS once per workgroup.  Three waves per SIMD
+// (at most 168 registers): the network's accumulators then stay in ordinary
+// registers (no accumulator-register reads) and a third wave hides more of
+// the LDS and matrix-core latency.
 template <class ST, bool MASKED>
-__global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t g0, int32_t n) {
+__global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32_t g0, int32_t n) {
   using T = typename ST::T;
-  __shared__ __attribute__((aligned(16))) __bf16 wl[kWPackedElems];
+  __shared__ __attribute__((aligned(16))) __bf16 wl[kWStageElems];
   stage_weights(wl, (const __bf16 *)a.mlp_w);
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6;
@@ -151,8 +154,11 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
 #pragma unroll
     for (int d = 0; d < kNbr; ++d) bm[d] = a.bbm[(size_t)b * kNbr + d];
   }
-  float h[Q];
-  h[0] = ST::load(src, pidx(0, own_slot));
+  // all stored values first, then their decoding: under the register limit
+  // of three waves per SIMD this keeps the 19 loads of 16-bit storage in
+  // flight together instead of one converted value at a time
+  T raw[Q];
+  raw[0] = src[pidx(0, own_slot)];
   static_for<1, Q>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     uint32_t slot = pull_slot<i>(lane, b, nbv);
@@ -163,60 +169,81 @@ __global__ __launch_bounds__(256) void k_block_interior_mlp(StepArgs a, int32_t 
         plane = kOpp[i];
       }
     }
-    h[i] = ST::load(src, pidx(plane, slot));
+    raw[i] = src[pidx(plane, slot)];
   });
+  float h[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) h[i] = ST::decode(raw[i]);
   const bool fluid = MASKED ? ((a.fmask[b] >> lane) & 1ull) != 0 : true;
 
-  // closure inputs g = (f - f^eq)/rho, standardized
+  // closure inputs g = (f - f^eq)/rho, standardized.  What the rest of the
+  // update needs of the populations -- the moments and the non-equilibrium
+  // stress (the regularized operator's input, for the judge and the
+  // fallback) -- is taken now, so the populations are dead while the
+  // network runs (fewer live registers, more waves per SIMD); the
+  // equilibrium is recomputed afterwards, bit for bit the same.
   const Moments m = moments(h);
-  float heq[Q];
-  equilibrium(m, heq);
   const float *sd = a.mlp_stdz;
   const float ir = 1.0f / m.rho;
   float x[Q];
   bool out_of_range = false;
+  {
+    float heq[Q];
+    equilibrium(m, heq);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float g = (h[i] - heq[i]) * ir;
-    x[i] = fluid ? (g - sd[i]) * sd[32 + i] : 0.0f;
-    out_of_range = out_of_range || fabsf(x[i]) > 8.0f;
+    for (int i = 0; i < Q; ++i) {
+      const float g = (h[i] - heq[i]) * ir;
+      x[i] = fluid ? (g - sd[i]) * sd[32 + i] : 0.0f;
+      out_of_range = out_of_range || fabsf(x[i]) > 8.0f;
+    }
   }
+  float pneq[6];
+  neq_stress(h, m, pneq);
   float y[Q];
   mlp_forward_wave_reg(x, y, wl, a.mlp_bias, lane);
 #pragma unroll
   for (int i = 0; i < Q; ++i) y[i] = fmaf(y[i], sd[64 + i], sd[96 + i]);
-  project_out(y);
+  float ys[6];  // second-order Hermite coordinates of the closure's output
+  q_stress(y, ys);
+  hermite2(ys[0], ys[1], ys[2], ys[3], ys[4], ys[5], y);
   // the regularized operator judges the closure: its non-equilibrium part
   // f1/rho must lie within judge (relative L2) of the closure's, with the
-  // typical target size as floor for voxels near equilibrium
+  // typical target size as floor for voxels near equilibrium.  Both are
+  // second-order Hermite vectors, so their distance and the target's size
+  // are taken from the six stress coordinates in closed form.
   bool off = false;
   if (a.mlp_judge > 0.0f) {
-    float f1[Q];
-    f1_projection(h, m, f1);
-    float d2 = 0.0f, t2 = 0.0f, s2 = 0.0f;
+    float ps[6], ds[6];  // coordinates of f1/rho and of the difference
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const float t = f1[i] * ir;
-      const float d = y[i] - t;
-      d2 = fmaf(d, d, d2);
-      t2 = fmaf(t, t, t2);
-      s2 = fmaf(sd[64 + i], sd[64 + i], s2);
+    for (int k = 0; k < 6; ++k) {
+      ps[k] = pneq[k] * ir;
+      ds[k] = ys[k] - ps[k];
     }
+    const float d2 = hermite2_norm2(ds[0], ds[1], ds[2], ds[3], ds[4], ds[5]);
+    const float t2 = hermite2_norm2(ps[0], ps[1], ps[2], ps[3], ps[4], ps[5]);
+    float s2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s2 = fmaf(sd[64 + i], sd[64 + i], s2);
     off = d2 > a.mlp_judge * a.mlp_judge * (t2 + s2);
   }
-  float hs[Q];
+  float heq[Q];
+  equilibrium(m, heq);
   const float r = (1.0f - a.omega) * m.rho;
   bool negative = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    hs[i] = fmaf(r, y[i], heq[i]);
-    negative = negative || (weight_f(i) + hs[i] < 0.0f);
+    h[i] = fmaf(r, y[i], heq[i]);
+    negative = negative || (weight_f(i) + h[i] < 0.0f);
   }
   const bool fb = fluid && (out_of_range || negative || off);
-  if (fb) collide_regularized_m(h, m, a.omega);
-  else
+  if (fb) {
+    // the regularized operator: f^eq + (1 - omega) f1, f1 from the stress
+    float f1[Q];
+    hermite2(pneq[0], pneq[1], pneq[2], pneq[3], pneq[4], pneq[5], f1);
+    const float rr = 1.0f - a.omega;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) h[i] = hs[i];
+    for (int i = 0; i < Q; ++i) h[i] = fmaf(rr, f1[i], heq[i]);
+  }
   const uint64_t bal = __ballot(fb);
   if (lane == 0 && bal) atomicAdd(a.mlp_fallbacks, (unsigned long long)__popcll(bal));
 #pragma unroll
@@ -460,15 +487,16 @@ __global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g
 // workgroup); consecutive workgroups go to different XCDs, which spreads
 // every group over the whole chip.  Each block runs the body of its
 // group's own kernel.
-template <class ST, int COLL, bool FUSED>
-__global__ __launch_bounds__(256) void k_level_merged(StepArgs a, MrArgs m, int32_t nj, int32_t nbd, int32_t nm,
-                                                      int32_t nf) {
+// JFUSED selects the jump group's form separately (the paper's schedule
+// streams jump blocks unfused while the uniform groups are fused).
+template <class ST, int COLL, bool FUSED, bool JFUSED>
+__device__ __forceinline__ void level_merged_body(const StepArgs &a, const MrArgs &m, int32_t nj, int32_t nbd,
+                                                  int32_t nm, int32_t nf, int k) {
   const int wave = (int)(threadIdx.x >> 6);
-  int k = (int)blockIdx.x;
   const int wj = (nj + 3) >> 2, wb = (nbd + 3) >> 2, wm = (nm + 3) >> 2;
   if (k < wj) {
     const int b = __builtin_amdgcn_readfirstlane(k * 4 + wave);
-    if (b < nj) mr_jump_block<ST, COLL, FUSED>(a, m, b);
+    if (b < nj) mr_jump_block<ST, COLL, JFUSED>(a, m, b);
     return;
   }
   k -= wj;
@@ -486,6 +514,27 @@ __global__ __launch_bounds__(256) void k_level_merged(StepArgs a, MrArgs m, int3
   k -= wm;
   const int b = __builtin_amdgcn_readfirstlane(k * 4 + wave);
   if (b < nf) interior_block<ST, COLL, false, FUSED>(a, nj + nbd + nm + b);
+}
+
+template <class ST, int COLL, bool FUSED, bool JFUSED = FUSED>
+__global__ __launch_bounds__(256) void k_level_merged(StepArgs a, MrArgs m, int32_t nj, int32_t nbd, int32_t nm,
+                                                      int32_t nf) {
+  level_merged_body<ST, COLL, FUSED, JFUSED>(a, m, nj, nbd, nm, nf, (int)blockIdx.x);
+}
+
+// Two merged level updates with no buffer in common between one's writes
+// and the other's reads or writes -- a coarse level's update and the next
+// substep of a level two or more levels finer, or of the finer level's
+// second substep, whose reads are the coarse level's current state and
+// not the buffer being written -- in one launch: the first update's
+// workgroups, then the second's.
+template <class ST, int COLL>
+__global__ __launch_bounds__(256) void k_level_pair(StepArgs a0, MrArgs m0, int4 c0, StepArgs a1, MrArgs m1,
+                                                    int4 c1) {
+  const int k = (int)blockIdx.x;
+  const int w0 = ((c0.x + 3) >> 2) + ((c0.y + 3) >> 2) + ((c0.z + 3) >> 2) + ((c0.w + 3) >> 2);
+  if (k < w0) level_merged_body<ST, COLL, true, true>(a0, m0, c0.x, c0.y, c0.z, c0.w, k);
+  else level_merged_body<ST, COLL, true, true>(a1, m1, c1.x, c1.y, c1.z, c1.w, k - w0);
 }
 
 #endif  // LBM_Q27
@@ -634,8 +683,21 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
       const int32_t *c = L.gcount;
       const dim3 gm((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4);
       if (g0 != 0 || c[0] + c[1] + c[2] + c[3] != n) return hipErrorInvalidValue;
-      if (f) hipLaunchKernelGGL((k_level_merged<ST, COLL, true>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
+      if (L.fused == 2)  // uniform groups fused, jump group streamed only
+        hipLaunchKernelGGL((k_level_merged<ST, COLL, true, false>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2],
+                           c[3]);
+      else if (f)
+        hipLaunchKernelGGL((k_level_merged<ST, COLL, true>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
       else hipLaunchKernelGGL((k_level_merged<ST, COLL, false>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
+      break;
+    }
+    case kKernelLevelPair: {
+      const int32_t *c = L.gcount, *d = L.gcount2;
+      const dim3 gm((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4 + (d[0] + 3) / 4 +
+                    (d[1] + 3) / 4 + (d[2] + 3) / 4 + (d[3] + 3) / 4);
+      if (!f) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_level_pair<ST, COLL>), gm, blk, 0, s, L.args, L.mr, make_int4(c[0], c[1], c[2], c[3]),
+                         L.args2, L.mr2, make_int4(d[0], d[1], d[2], d[3]));
       break;
     }
 #endif
@@ -676,7 +738,8 @@ hipError_t launch_one(const Launch &L, int32_t storage, int32_t collision, hipSt
 #else
     // the closure runs on the non-boundary groups; every other kernel uses
     // the regularized operator it was trained to imitate
-    if (L.kind == kKernelLevelMerged) return hipErrorInvalidValue;  // never scheduled with the closure
+    if (L.kind == kKernelLevelMerged || L.kind == kKernelLevelPair)
+      return hipErrorInvalidValue;  // never scheduled with the closure
     if (L.fused && (L.kind == kKernelFull || L.kind == kKernelMasked)) {
       switch (storage) {
         case LBM_F32: return launch_mlp<StoreF32>(L, s);

@@ -21,7 +21,7 @@ LBM_OK = 0
 DENSE, BLOCK_SPARSE, MULTIRES = 0, 1, 2
 F32, F16_SHIFTED, BF16_SHIFTED = 0, 1, 2
 BGK, REGULARIZED, MLP = 0, 1, 2
-PLAIN_SINGLE_KERNEL, DISAGG, DISAGG_BITMASK = 0, 1, 2
+PLAIN_SINGLE_KERNEL, DISAGG, DISAGG_BITMASK, DISAGG_UNIFORM_FUSED = 0, 1, 2, 3
 XMIN, XMAX, YMIN, YMAX, ZMIN, ZMAX = range(6)
 BC_BOUNCE_BACK, BC_MOVING_WALL, BC_REG_VELOCITY, BC_REG_PRESSURE = range(4)
 MAP_GROUPS, MAP_COORDS, MAP_NEIGHBOURS, MAP_FLUIDMASK, MAP_CANONICAL, MAP_BOUNDARY_BITS, MAP_RECORD_IDS = range(7)
@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
             "lbm_mlp_forward": ([vp, vp, i64, vp, vp], i32),
             "lbm_mlp_gradients": ([vp, vp, vp, i64, vp, vp, vp], i32),
             "lbm_mlp_train_step": ([vp, vp, vp, i64, ctypes.c_float, i32, vp, vp], i32),
+            "lbm_mlp_adam": ([vp, vp, ctypes.c_float, i32, vp], i32),
+            "lbm_mlp_init_params": ([vp, ctypes.c_uint64, vp], i32),
             "lbm_mlp_set_judge": ([vp, ctypes.c_double], i32),
             "lbm_mlp_fallbacks": ([vp, ctypes.POINTER(ctypes.c_uint64), i32, vp], i32),
             "lbm_mlp_destroy": ([vp], i32),
@@ -254,6 +256,14 @@ def lbm_mlp_train_step(m, f_ptr: int, idx_ptr, n: int, lr: float, t: int, loss_p
                        stream=None) -> None:
     check(lib().lbm_mlp_train_step(m, f_ptr, idx_ptr, int(n), float(lr), int(t), loss_ptr,
                                    _stream_ptr(stream)))
+
+
+def lbm_mlp_adam(m, grads_ptr: int, lr: float, t: int, stream=None) -> None:
+    check(lib().lbm_mlp_adam(m, grads_ptr, float(lr), int(t), _stream_ptr(stream)))
+
+
+def lbm_mlp_init_params(m, seed: int, stream=None) -> None:
+    check(lib().lbm_mlp_init_params(m, int(seed) & 0xFFFFFFFFFFFFFFFF, _stream_ptr(stream)))
 
 
 def lbm_mlp_set_judge(m, rel_tol: float) -> None:
@@ -483,6 +493,14 @@ class Mlp:
         n = f.shape[0] if idx is None else idx.shape[0]
         lbm_mlp_train_step(self.h, f.data_ptr(), None if idx is None else idx.data_ptr(), n, lr, t,
                            None if loss is None else loss.data_ptr())
+
+    def adam(self, grads, lr: float, t: int) -> None:
+        """Adam step t on caller gradients (FP32 device tensor [MLP_PARAMS])."""
+        lbm_mlp_adam(self.h, grads.data_ptr(), lr, t)
+
+    def init_params(self, seed: int) -> None:
+        """Seeded He-uniform weights and zero biases, drawn on the device."""
+        lbm_mlp_init_params(self.h, seed)
 
     def set_judge(self, rel_tol: float) -> None:
         lbm_mlp_set_judge(self.h, rel_tol)

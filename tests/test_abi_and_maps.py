@@ -269,8 +269,13 @@ def test_launch_structure_bitmask_grouping():
 def test_multires_merged_level_updates():
     """A multires level with at most the merge limit of blocks runs each of
     its updates as one launch over all its blocks (2^(L-1-l) updates of
-    level l per coarse step); limit 0 gives one launch per non-empty group;
-    a negative limit is rejected."""
+    level l per coarse step).  With every group fused, a coarse level's
+    update and the finer level's next update share no buffer one writes and
+    the other uses, so they pair into one launch: the 7 level updates of a
+    3-level coarse step (levels 0, 1, 0, 2, 0, 1, 0) run as 4 launches
+    (0 | 1+0 | 2+0 | 1+0).  The other schedules keep one launch per update.
+    Limit 0 gives one launch per non-empty group; a negative limit is
+    rejected."""
     n, levels = 64, 3
     lm = workloads.multires_cavity(n)
     faces = {f: (lbm.BC_BOUNCE_BACK, (0, 0, 0)) for f in range(6)}
@@ -281,7 +286,14 @@ def test_multires_merged_level_updates():
     totals = [int(x[4]) for x in groups]
     assert max(totals) <= 8192
     merged = g.launches()
-    assert sorted(merged) == sorted(t for l, t in enumerate(totals) for _ in range(2 ** (levels - 1 - l)))
+    t0, t1, t2 = totals
+    assert merged == [t0, t1 + t0, t2 + t0, t1 + t0]
+    for sch in (lbm.DISAGG_UNIFORM_FUSED, lbm.PLAIN_SINGLE_KERNEL):
+        gs = lbm.Grid(n, n, n, kind=lbm.MULTIRES, levels=levels, level_map=lm, periodic=(False,) * 3,
+                      faces=faces, schedule=sch, device="cpu")
+        ls = gs.launches()
+        assert len(ls) >= 7 and t1 + t0 not in ls and t2 + t0 not in ls, (sch, ls)
+        gs.close()
     g.set_merge_limit(0)
     separate = g.launches()
     per_level = [[int(c) for c in x[:4] if c > 0] for x in groups]

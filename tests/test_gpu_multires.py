@@ -103,15 +103,15 @@ def test_multires_periodic_vs_oracle(orc, levels, n, storage, bar):
 
 @pytest.mark.parametrize("collision", [0, 1])
 def test_multires_fused_equals_unfused_bitwise(orc, collision):
-    """Fused and unfused schedules, each with merged level updates (the
-    default for small levels) and with one launch per group, agree bit for
-    bit."""
+    """Fused, unfused and the paper's schedule (uniform blocks fused, jump
+    blocks unfused), each with merged level updates (the default for small
+    levels) and with one launch per group, agree bit for bit."""
     n, levels = (64, 32, 32), 3
     lm = blob_level_map(n, levels, (32, 16, 16), 6.0)
     og = orc.MultiresGrid(*n, levels=levels, level_map=lm, tau_coarsest=0.56)
     rho, u = random_fields(og, 5)
     pops = []
-    for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG):
+    for sch in (lbm.PLAIN_SINGLE_KERNEL, lbm.DISAGG, lbm.DISAGG_UNIFORM_FUSED):
         for limit in (None, 0):
             _, g, _, _ = run_pair(orc, n, levels, lm, None, (True,) * 3, {}, 0.56, 6, rho, u, schedule=sch,
                                   collision=collision, oracle=False, merge_limit=limit)
@@ -154,7 +154,7 @@ def test_multires_sphere_tunnel_vs_oracle(orc):
         u.append(uu)
     pops = []
     for sch, limit in ((lbm.PLAIN_SINGLE_KERNEL, None), (lbm.DISAGG, None), (lbm.PLAIN_SINGLE_KERNEL, 0),
-                       (lbm.DISAGG, 0)):
+                       (lbm.DISAGG, 0), (lbm.DISAGG_UNIFORM_FUSED, None)):
         og, g, out, ref = run_pair(orc, n, levels, lm, fluid, (False, True, True), faces, 0.52, 20, rho, u,
                                    schedule=sch, oracle=(sch == lbm.DISAGG and limit is None), merge_limit=limit)
         pops.append([g.populations(level=l).cpu().numpy() for l in range(levels)])
@@ -183,7 +183,7 @@ def test_multires_lid_driven_cavity_vs_oracle(orc):
     u = [np.zeros(og.shape(l) + (3,)) for l in range(levels)]
     pops = []
     for sch, limit in ((lbm.PLAIN_SINGLE_KERNEL, None), (lbm.DISAGG, None), (lbm.PLAIN_SINGLE_KERNEL, 0),
-                       (lbm.DISAGG, 0)):
+                       (lbm.DISAGG, 0), (lbm.DISAGG_UNIFORM_FUSED, None)):
         og, g, out, ref = run_pair(orc, n, levels, lm, None, (False,) * 3, faces, 0.52, 30, rho, u,
                                    schedule=sch, oracle=(sch == lbm.DISAGG and limit is None), merge_limit=limit)
         pops.append([g.populations(level=l).cpu().numpy() for l in range(levels)])
@@ -192,6 +192,46 @@ def test_multires_lid_driven_cavity_vs_oracle(orc):
                 a = og.active(l)
                 err = rel(out[l][1], ref[l][1][a])
                 _say(f"  cavity level {l}: rel L2 u = {err:.3e}")
+                assert err < 1e-5
+            m0 = sum(float(np.sum(rho[l][og.active(l)])) * 8 ** l for l in range(levels))
+            m1 = g.reduce().cpu().numpy()[0]
+            _say(f"  mass drift {abs(m1 - m0) / m0:.2e}")
+            assert abs(m1 - m0) / m0 < 1e-6
+        g.close()
+    for k in range(1, len(pops)):
+        for l in range(levels):
+            assert np.array_equal(pops[0][l], pops[k][l]), (k, l)
+
+
+def test_multires_four_levels_vs_oracle(orc):
+    """Four levels (the 4-level rows of table multiResLbm): the lid-driven
+    cavity refined towards the walls on a 128^3 box (692,224 / 65,024 /
+    9,728 / 512 voxels on levels 0-3; coarsest blocks of 32^3 finest cells);
+    every schedule within 1e-5 of the FP64 oracle on every level and
+    bit-identical to each other, mass conserved."""
+    n, levels = (128, 128, 128), 4
+    lm = workloads.multires_cavity(128, levels=4, shells=(8, 8, 8))
+    assert all(np.any(lm == l) for l in range(levels))
+    faces = {f: (lbm.BC_BOUNCE_BACK, (0, 0, 0)) for f in range(6)}
+    faces[lbm.ZMAX] = (lbm.BC_MOVING_WALL, (0.1, 0.0, 0.0))
+    og = orc.MultiresGrid(*n, levels=levels, level_map=lm, periodic=(False,) * 3, tau_coarsest=0.51)
+    rho = [np.ones(og.shape(l)) for l in range(levels)]
+    u = [np.zeros(og.shape(l) + (3,)) for l in range(levels)]
+    pops = []
+    for sch, limit in ((lbm.DISAGG, None), (lbm.PLAIN_SINGLE_KERNEL, None), (lbm.DISAGG_UNIFORM_FUSED, None),
+                       (lbm.DISAGG, 0)):
+        # 32 coarse steps (256 finest): the lid's sound waves cross the box
+        # and reach the level-3 core, whose velocity is then well above
+        # FP32 rounding of the stored populations
+        og, g, out, ref = run_pair(orc, n, levels, lm, None, (False,) * 3, faces, 0.51, 32, rho, u,
+                                   schedule=sch, oracle=(sch == lbm.DISAGG and limit is None), merge_limit=limit)
+        pops.append([g.populations(level=l).cpu().numpy() for l in range(levels)])
+        if ref is not None:
+            for l in range(levels):
+                a = og.active(l)
+                err = rel(out[l][1], ref[l][1][a])
+                _say(f"  4-level cavity level {l} ({int(a.sum())} voxels): rel L2 u = {err:.3e}, "
+                     f"rms |u| {np.sqrt(np.mean(np.sum(ref[l][1][a] ** 2, axis=1))):.2e}")
                 assert err < 1e-5
             m0 = sum(float(np.sum(rho[l][og.active(l)])) * 8 ** l for l in range(levels))
             m1 = g.reduce().cpu().numpy()[0]
