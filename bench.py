@@ -20,7 +20,7 @@ sphere and the multires lid-driven cavity (unfused baseline against fused),
 the regularized operator and the learned closure (with the share of HBM and
 matrix-core peak of its interior launch).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--arms all|none|closure|storage]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--arms all|none|closure|storage|table]
 """
 from __future__ import annotations
 
@@ -195,9 +195,10 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--arms", default="all", choices=["all", "none", "closure", "storage"],
+    ap.add_argument("--arms", default="all", choices=["all", "none", "closure", "storage", "table"],
                     help="closure: only the learned-closure arms; storage: only the 16-bit cavity "
-                         "arms (both for counter runs)")
+                         "arms (both for counter runs); table: the 320^3 and 480^3 multires "
+                         "cavity rows of table multiResLbm")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (torch) 5 times, the reference "
@@ -261,7 +262,7 @@ def main(argv=None) -> int:
     torch.cuda.empty_cache()
 
     arms = {}
-    if args.arms in ("all", "closure", "storage"):
+    if args.arms in ("all", "closure", "storage", "table"):
         def arm(name, make, steps, bytes_per_update, interior=None):
             log(name)
             gg = make()
@@ -343,6 +344,19 @@ def main(argv=None) -> int:
         arm("taylor_green256_re1600_f32_regularized",
             lambda: cases.taylor_green(collision=lbm.REGULARIZED), 100, 152)
         arm("taylor_green256_re1600_f32_bgk", lambda: cases.taylor_green(collision=lbm.BGK), 100, 152)
+
+    if args.arms == "table":
+        # the other sizes of table multiResLbm (320^3 and 480^3, 3 and 4
+        # levels), each schedule; not in the default run (every grid takes
+        # some seconds to build on the host)
+        mr_schedules = ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"),
+                        (lbm.DISAGG_UNIFORM_FUSED, "paper_uniform_fused"), (lbm.DISAGG, "disagg_fused"))
+        for n in (320, 480):
+            for levels in (3, 4):
+                for sch, nm in mr_schedules:
+                    arm(f"multires_cavity{n}_{levels}lvl_f32_{nm}",
+                        lambda n=n, levels=levels, sch=sch: cases.multires_cavity(n=n, schedule=sch, levels=levels),
+                        10, 152)
 
     if args.arms in ("all", "closure"):
         # the learned closure in place of the collision operator

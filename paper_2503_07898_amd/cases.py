@@ -76,16 +76,26 @@ def multires_sphere(storage=lbm.F32, schedule=lbm.DISAGG, scale=1, collision=lbm
     return g
 
 
+# Refinement shells (finest cells from the walls, per level boundary) that
+# reproduce the voxel distributions of table multiResLbm (millions of
+# voxels per level, finest first):
+#   320^3: 16.0 / 1.21 / 0.11 ("15, 1, 0.1"), 4 levels 16.0 / 1.21 / 0.078 / 0.004 ("15, 1, 0.1, 0.002")
+#   480^3: 54.0 / 4.09 / 0.37 ("53, 4, 0.4"), 4 levels 54.0 / 4.09 / 0.31 / 0.008 ("53, 4, 0.3, 0.008")
+#   512^3: 77.6 / 4.09 / 0.37 ("77, 4, 0.4"), 4 levels 77.6 / 2.98 / 0.48 / 0.004 ("73, 3, 0.5, 0.003")
+TABLE_SHELLS = {(320, 3): (32, 24), (320, 4): (32, 24, 32), (480, 3): (48, 48), (480, 4): (48, 48, 64),
+                (512, 3): (64, 48), (512, 4): (64, 32, 96)}
+
+
 def multires_cavity(n=512, storage=lbm.F32, schedule=lbm.DISAGG, tau=0.52, uw=0.1, collision=lbm.BGK,
                     levels=3, shells=None):
     """Multi-resolution lid-driven cavity: closed n^3 box (finest
     resolution) refined towards the walls, bounce-back walls, lid z+ moving
-    with (uw, 0, 0) on the finest level, tau at the coarsest level.  Three
-    levels by default (57.8% / 24.4% / 17.8% of the volume on levels
-    0 / 1 / 2 at n = 512: 77.6M / 4.09M / 0.37M voxels); with levels=4 the
-    shells (64, 32, 96) at n = 512 give 77.6M / 2.98M / 0.48M / 0.004M
-    voxels (the 4-level rows of table multiResLbm: 73 / 3 / 0.5 / 0.003)."""
-    if levels == 4 and shells is None:
+    with (uw, 0, 0) on the finest level, tau at the coarsest level.  The
+    shells default to TABLE_SHELLS for the table's sizes (512^3, 3 levels:
+    77.6M / 4.09M / 0.37M voxels), else to (n/8, 3n/32[, 3n/16])."""
+    if shells is None:
+        shells = TABLE_SHELLS.get((n, levels))
+    if shells is None and levels == 4:
         shells = (n // 8, n // 16, 3 * n // 16)
     lm = workloads.multires_cavity(n, levels=levels, shells=shells)
     faces = {f: (lbm.BC_BOUNCE_BACK, (0, 0, 0)) for f in range(6)}

@@ -159,7 +159,7 @@ def run_gain(orc, n, re, resolved=True):
         row["ke_curve_rel"] = [round(res[s][0] / ref[s][0] - 1.0, 6) if s in res and s in ref else None
                                for s in checkpoints]
         table[name] = row
-        errs = "  ".join(f"u@{lab[8:]} {row[lab]:.3e}" for lab in row if lab.startswith("rel_l2_u_"))
+        errs = "  ".join(f"u@{lab[9:]} {row[lab]:.3e}" for lab in row if lab.startswith("rel_l2_u_"))
         _say(f"  {name:22s} {errs}  first non-finite step {bad}  mass drift {drift:.1e}  "
              f"fallback fraction {fb:.3f}")
     _say("  GAIN " + json.dumps({"n": n, "re": re, "tau": tau, "checkpoints": checkpoints,
