@@ -107,7 +107,7 @@ def time_launch(torch, lbm, g, k: int, reps: int) -> float:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("device_common.h", "step_kernels.hip", "launch.h", "lattice.h", "mlp_device.h"):
+    for f in ("device_common.h", "step_kernels.hip", "launch.h", "lattice.h", "mlp_device.h", "api.cpp"):
         with open(os.path.join(ROOT, "paper_2503_07898_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -350,6 +350,21 @@ lbm_status lbm_set_collision(lbm_grid *g, lbm_collision c, const lbm_mlp *m);
  * effect at the next step.  max_blocks < 0 is LBM_ERR_INVALID_ARG. */
 lbm_status lbm_set_merge_limit(lbm_grid *g, int64_t max_blocks);
 
+/* Residency cap of the stepping kernels (a tuning knob; results are bit for
+ * bit the same either way).  Each 256-thread workgroup of the block kernels
+ * (every kernel of lbm_step except the closure's) requests LDS it never
+ * touches, (LDS per CU) / wg_per_cu bytes rounded down to 1 KiB, so that at
+ * most wg_per_cu workgroups (4 waves each) sit on one compute unit.  Fewer
+ * blocks in flight keep the rows a block pulls from its neighbours in L2
+ * until the neighbour reads them too, at the price of fewer loads in
+ * flight.  0 removes the cap (registers then allow up to 8 per CU);
+ * LBM_RESIDENCY_AUTO (the default) takes a per-kernel value measured on
+ * MI355X for the kernel kind, storage and lattice.  Any grid state; takes
+ * effect at the next launch.  Values outside LBM_RESIDENCY_AUTO..8 are
+ * LBM_ERR_INVALID_ARG. */
+#define LBM_RESIDENCY_AUTO (-1)
+lbm_status lbm_set_residency(lbm_grid *g, int32_t wg_per_cu);
+
 /* n pre-collision population sets (FP32, unshifted, [n][19]: the values the
  * collision operator of the next step receives, pulled from the current
  * post-collision field with bounce-back) of fluid voxels drawn uniformly

@@ -99,6 +99,9 @@ struct lbm_grid {
   lbm_grid_desc desc{};
   int32_t q = 19;  // lattice
   int64_t merge_max = kMergeMaxBlocks;  // multires: merged level updates up to this many blocks
+  int32_t residency = LBM_RESIDENCY_AUTO;  // workgroups per CU of the block kernels, 0 = no cap
+  bool lds_sized = false;                  // lds_of filled for the current device
+  uint32_t lds_of[9] = {};                 // LDS bytes per workgroup that cap residency at w
   LatticeLaunchers ops = LBM_LAUNCHERS_OF(lbm::k19);
   int32_t collision = LBM_BGK;
   const lbm_mlp *mlp = nullptr;
@@ -667,15 +670,58 @@ lbm_status lbm_init_equilibrium(lbm_grid *g, int32_t level, const double *rho, c
   return LBM_OK;
 }
 
+// LDS bytes per workgroup that leave room for at most w workgroups on one
+// CU of the current device (1 KiB steps), w = 1..8; 0 requests none
+static lbm_status size_residency(lbm_grid *g) {
+  int dev = 0, per_cu = 0, per_wg = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&per_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return hip_fail(e, "LDS size query");
+  g->lds_of[0] = 0;
+  for (int w = 1; w <= 8; ++w) {
+    const int64_t b = ((int64_t)per_cu / w) / 1024 * 1024;
+    g->lds_of[w] = (uint32_t)(b < per_wg ? b : (int64_t)per_wg / 1024 * 1024);
+  }
+  g->lds_sized = true;
+  return LBM_OK;
+}
+
+// Workgroups per CU of each block kernel under LBM_RESIDENCY_AUTO (0: no
+// cap), from sweeps of every kernel kind, storage and lattice on MI355X.
+// Launches of fewer than 65536 blocks are not capped: with under 64
+// workgroups per CU they need every wave slot for loads in flight.
+static int32_t auto_residency(const Launch &x, int32_t storage, int32_t q) {
+  if (x.count < 65536) return 0;
+  const bool f32 = storage == LBM_F32, q19 = q == 19;
+  switch (x.kind) {
+    case kKernelFull: return f32 ? 5 : (q19 ? 6 : 5);
+    case kKernelMasked: return f32 ? 5 : (q19 ? 7 : 0);
+    case kKernelInteriorBits: return q19 ? (f32 ? 5 : 7) : 0;
+    case kKernelBoundary: return q19 ? (f32 ? 6 : 7) : 0;
+    case kKernelJump: return f32 ? 5 : 0;
+    default: return 0;
+  }
+}
+
+static uint32_t residency_lds(const lbm_grid *g, const Launch &x) {
+  const int32_t w = g->residency >= 0 ? g->residency : auto_residency(x, g->desc.storage, g->q);
+  return g->lds_of[w < 0 ? 0 : (w > 8 ? 8 : w)];
+}
+
 lbm_status lbm_step(lbm_grid *g, int32_t n, void *stream) {
   if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
   if (g->state < kReady) return fail(LBM_ERR_STATE, "initialise the populations first");
   if (n < 0) return fail(LBM_ERR_INVALID_ARG, "negative step count");
   const float judge = g->mlp ? g->mlp->judge : 0.0f;  // may change between steps
+  if (!g->lds_sized) {
+    if (lbm_status st = size_residency(g)) return st;
+  }
   for (int32_t k = 0; k < n; ++k) {
     const lbm_grid::StepPlan &p = step_plan(g);
     for (Launch x : p.launches) {
       x.args.mlp_judge = judge;
+      x.lds = residency_lds(g, x);
       hipError_t e = g->ops.one(x, g->desc.storage, coll_code(g), (hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "step launch");
     }
@@ -706,6 +752,10 @@ lbm_status lbm_launch_group(lbm_grid *g, int32_t k, void *stream) {
   std::vector<Launch> launches;
   step_launches(g, tmp, launches);
   if (k < 0 || k >= (int32_t)launches.size()) return fail(LBM_ERR_INVALID_ARG, "launch index out of range");
+  if (!g->lds_sized) {
+    if (lbm_status st = size_residency(g)) return st;
+  }
+  launches[k].lds = residency_lds(g, launches[k]);
   hipError_t e = g->ops.one(launches[k], g->desc.storage, coll_code(g), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "launch_group");
   return LBM_OK;
@@ -1061,6 +1111,14 @@ lbm_status lbm_set_merge_limit(lbm_grid *g, int64_t max_blocks) {
   if (max_blocks < 0) return fail(LBM_ERR_INVALID_ARG, "the merge limit must be >= 0");
   g->merge_max = max_blocks;
   g->plans.clear();
+  return LBM_OK;
+}
+
+lbm_status lbm_set_residency(lbm_grid *g, int32_t wg_per_cu) {
+  if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
+  if (wg_per_cu < LBM_RESIDENCY_AUTO || wg_per_cu > 8)
+    return fail(LBM_ERR_INVALID_ARG, "workgroups per CU must be LBM_RESIDENCY_AUTO or in 0..8");
+  g->residency = wg_per_cu;
   return LBM_OK;
 }
 

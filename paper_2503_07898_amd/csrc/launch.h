@@ -69,6 +69,8 @@ struct Launch {
   int32_t fused;          // 0: store the gathered (pre-collision) populations only; 2 (merged
                           // level launch): uniform groups fused, jump group stored only
   int32_t first, count;   // block range of the launch
+  uint32_t lds;           // dynamic LDS bytes the kernel never touches: requested only to cap the
+                          // workgroups resident per CU (0: no cap)
   int32_t gcount[4];      // kKernelLevelMerged: blocks of the jump, boundary, masked, full groups
   StepArgs args;
   MrArgs mr;

@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
             "lbm_mlp_destroy": ([vp], i32),
             "lbm_set_collision": ([vp, i32, vp], i32),
             "lbm_set_merge_limit": ([vp, i64], i32),
+            "lbm_set_residency": ([vp, i32], i32),
             "lbm_check": ([vp, vp], i32),
             "lbm_sample_populations": ([vp, i32, ctypes.c_uint64, i64, vp, vp], i32),
             "lbm_grid_destroy": ([vp], i32),
@@ -201,6 +202,7 @@ def lbm_launch_group(g, k: int, stream=None) -> None:
     check(lib().lbm_launch_group(g, int(k), _stream_ptr(stream)))
 
 
+RESIDENCY_AUTO = -1  # lbm_set_residency: per-kernel measured caps
 MLP_PARAMS = 6675
 MLP_BATCH_MAX = 8192
 
@@ -290,6 +292,10 @@ def lbm_check(g, stream=None) -> None:
 
 def lbm_set_merge_limit(g, max_blocks: int) -> None:
     check(lib().lbm_set_merge_limit(g, int(max_blocks)))
+
+
+def lbm_set_residency(g, wg_per_cu: int) -> None:
+    check(lib().lbm_set_residency(g, int(wg_per_cu)))
 
 
 def lbm_sample_populations(g, level: int, seed: int, n: int, f_ptr: int, stream=None) -> None:
@@ -431,6 +437,11 @@ class Grid:
 
     def set_merge_limit(self, max_blocks: int) -> None:
         lbm_set_merge_limit(self.h, max_blocks)
+
+    def set_residency(self, wg_per_cu: int) -> None:
+        """Caps the stepping kernels at wg_per_cu resident workgroups per CU
+        (0: no cap, RESIDENCY_AUTO: the measured per-kernel default)."""
+        lbm_set_residency(self.h, wg_per_cu)
 
     def sample(self, seed: int, n: int, level: int = 0):
         import torch

@@ -305,6 +305,18 @@ def test_multires_merged_level_updates():
     g.close()
 
 
+def test_residency_setting_range():
+    """lbm_set_residency takes LBM_RESIDENCY_AUTO (-1), 0 (no cap) or 1..8
+    workgroups per CU, in any grid state, and rejects everything else."""
+    g = lbm.Grid(16, 16, 16, device="cpu")
+    for w in (lbm.RESIDENCY_AUTO, 0, 1, 5, 8):
+        g.set_residency(w)
+    for w in (-2, 9, 64):
+        with pytest.raises(lbm.LbmError):
+            g.set_residency(w)
+    g.close()
+
+
 @pytest.mark.parametrize("case", [0, 1, 4])
 @pytest.mark.parametrize("grouped", [True, False])
 def test_index_maps_d3q27(orc, case, grouped):

@@ -201,6 +201,29 @@ def test_sparse_tunnel_vs_oracle(orc, storage, bar, collision):
     assert np.array_equal(pops[0], pops[2])
 
 
+def test_residency_cap_leaves_results_bitwise():
+    """The residency cap only changes how many workgroups share a CU (the
+    block kernels request LDS they never touch); every launch of the
+    block-sparse tunnel (full, masked and boundary groups) gives the same
+    bits with no cap, caps of 1, 3 and 7, and the automatic choice."""
+    n, steps = (64, 32, 32), 20
+    fluid, faces = tunnel(n)
+    rho = np.ones((n[2], n[1], n[0]))
+    u = np.zeros(rho.shape + (3,))
+    u[..., 0] = 0.05 * fluid
+    out = []
+    for w in (0, 1, 3, 7, lbm.RESIDENCY_AUTO):
+        g = lbm.Grid(*n, fluid=fluid, kind=lbm.BLOCK_SPARSE, periodic=(False,) * 3, faces=faces,
+                     tau=0.6).bind()
+        g.set_residency(w)
+        g.init_equilibrium(canon(rho, fluid), canon(u, fluid).T.copy())
+        g.step(steps)
+        out.append(g.populations().cpu().numpy())
+        g.close()
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)
+
+
 def test_sparse_all_active_equals_dense_bitwise():
     n = (16, 16, 16)
     rho, u = workloads.taylor_green_2d(16, 0.05)
