@@ -676,19 +676,19 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
       break;
 #ifndef LBM_Q27
     case kKernelJump:
-      if (f) hipLaunchKernelGGL((k_mr_jump<ST, COLL, true>), grd, blk, L.lds, s, L.args, L.mr, g0, n);
-      else hipLaunchKernelGGL((k_mr_jump<ST, COLL, false>), grd, blk, L.lds, s, L.args, L.mr, g0, n);
+      if (f) hipLaunchKernelGGL((k_mr_jump<ST, COLL, true>), grd, blk, 0, s, L.args, L.mr, g0, n);
+      else hipLaunchKernelGGL((k_mr_jump<ST, COLL, false>), grd, blk, 0, s, L.args, L.mr, g0, n);
       break;
     case kKernelLevelMerged: {
       const int32_t *c = L.gcount;
       const dim3 gm((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4);
       if (g0 != 0 || c[0] + c[1] + c[2] + c[3] != n) return hipErrorInvalidValue;
       if (L.fused == 2)  // uniform groups fused, jump group streamed only
-        hipLaunchKernelGGL((k_level_merged<ST, COLL, true, false>), gm, blk, L.lds, s, L.args, L.mr, c[0], c[1], c[2],
+        hipLaunchKernelGGL((k_level_merged<ST, COLL, true, false>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2],
                            c[3]);
       else if (f)
-        hipLaunchKernelGGL((k_level_merged<ST, COLL, true>), gm, blk, L.lds, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
-      else hipLaunchKernelGGL((k_level_merged<ST, COLL, false>), gm, blk, L.lds, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
+        hipLaunchKernelGGL((k_level_merged<ST, COLL, true>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
+      else hipLaunchKernelGGL((k_level_merged<ST, COLL, false>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2], c[3]);
       break;
     }
     case kKernelLevelPair: {
@@ -696,7 +696,7 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
       const dim3 gm((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4 + (d[0] + 3) / 4 +
                     (d[1] + 3) / 4 + (d[2] + 3) / 4 + (d[3] + 3) / 4);
       if (!f) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_level_pair<ST, COLL>), gm, blk, L.lds, s, L.args, L.mr, make_int4(c[0], c[1], c[2], c[3]),
+      hipLaunchKernelGGL((k_level_pair<ST, COLL>), gm, blk, 0, s, L.args, L.mr, make_int4(c[0], c[1], c[2], c[3]),
                          L.args2, L.mr2, make_int4(d[0], d[1], d[2], d[3]));
       break;
     }

@@ -56,7 +56,7 @@ def random_fields(og, seed):
 
 
 def run_pair(orc, n, levels, lm, fluid, periodic, faces, tau, steps, rho, u, storage=lbm.F32,
-             schedule=lbm.DISAGG, collision=0, oracle=True, merge_limit=None):
+             schedule=lbm.DISAGG, collision=0, oracle=True, merge_limit=None, residency=None):
     okind = {lbm.BC_BOUNCE_BACK: orc.BB, lbm.BC_MOVING_WALL: orc.MOVING,
              lbm.BC_REG_VELOCITY: orc.REG_VEL, lbm.BC_REG_PRESSURE: orc.REG_PRES}
     bc = [(orc.BB, (0, 0, 0))] * 6
@@ -76,6 +76,8 @@ def run_pair(orc, n, levels, lm, fluid, periodic, faces, tau, steps, rho, u, sto
         g.init_equilibrium(rho[l][a], u[l][a].T.copy(), level=l)
     if merge_limit is not None:
         g.set_merge_limit(merge_limit)
+    if residency is not None:
+        g.set_residency(residency)
     g.step(steps)
     out = []
     for l in range(levels):
@@ -120,6 +122,29 @@ def test_multires_fused_equals_unfused_bitwise(orc, collision):
     for k in range(1, len(pops)):
         for l in range(levels):
             assert np.array_equal(pops[0][l], pops[k][l]), (k, l)
+
+
+def test_multires_residency_cap_bitwise(orc):
+    """Residency caps of 1 and 3 workgroups per CU and the automatic choice
+    leave every level bit for bit as without a cap, for the fused schedule
+    and the paper's, with merged level updates and with one launch per
+    group (the jump and merged-level kernels, which hold LDS of their own,
+    are launched uncapped)."""
+    n, levels = (64, 32, 32), 3
+    lm = blob_level_map(n, levels, (32, 16, 16), 6.0)
+    og = orc.MultiresGrid(*n, levels=levels, level_map=lm, tau_coarsest=0.56)
+    rho, u = random_fields(og, 9)
+    for sch in (lbm.DISAGG, lbm.DISAGG_UNIFORM_FUSED):
+        for limit in (None, 0):
+            pops = []
+            for w in (0, 1, 3, lbm.RESIDENCY_AUTO):
+                _, g, _, _ = run_pair(orc, n, levels, lm, None, (True,) * 3, {}, 0.56, 6, rho, u, schedule=sch,
+                                      oracle=False, merge_limit=limit, residency=w)
+                pops.append([g.populations(level=l).cpu().numpy() for l in range(levels)])
+                g.close()
+            for k in range(1, len(pops)):
+                for l in range(levels):
+                    assert np.array_equal(pops[0][l], pops[k][l]), (sch, limit, k, l)
 
 
 def test_multires_mass_conserved_on_gpu(orc):
