@@ -400,8 +400,8 @@ std::vector<float> gelu_table() {
   auto gelu = [](double x) { return 0.5 * x * (1.0 + std::tanh(0.7978845608028654 * (x + 0.044715 * x * x * x))); };
   std::vector<float> t(2 * kGeluSegs);
   const double h = 1.0 / kGeluPerUnit;
-  for (int j = 0; j < kGeluSegs; ++j) {
-    const double x0 = -8.0 + j * h, x1 = x0 + h;
+  for (int j = 0; j < kGeluSegs; ++j) {  // piece j is centred on -8 + j h
+    const double x0 = -8.0 + (j - 0.5) * h, x1 = x0 + h;
     const double a = (gelu(x1) - gelu(x0)) / h, b = gelu(x0) - a * x0;
     double dmin = 0.0, dmax = 0.0;
     for (int k = 1; k < 64; ++k) {

@@ -37,9 +37,10 @@ constexpr int kW1Elems = (kMlpInPad / 16) * (kMlpHidden / 32) * 64 * 8;   // 204
 constexpr int kW2Elems = (kMlpHidden / 16) * (kMlpHidden / 32) * 64 * 8;  // 4096
 constexpr int kW3Elems = (kMlpHidden / 16) * (kMlpOutPad / 32) * 64 * 8;  // 2048
 constexpr int kWPackedElems = kW1Elems + kW2Elems + kW3Elems;            // 8192 bf16 = 16 KB
-// GELU as a table of linear pieces: kGeluSegs segments of width
-// 1/kGeluPerUnit over [-8, 8), each (slope, intercept) as two floats; the
-// table follows the packed weights in device memory and in LDS.
+// GELU as a table of linear pieces: kGeluSegs pieces of width
+// 1/kGeluPerUnit centred on -8, -8 + 1/kGeluPerUnit, ..., each (slope,
+// intercept) as two floats; the table follows the packed weights in device
+// memory and in LDS.
 constexpr int kGeluPerUnit = 32;
 constexpr int kGeluSegs = 16 * kGeluPerUnit;                       // 512
 constexpr int kGeluTabBytes = kGeluSegs * 8;                       // 4 KB
@@ -87,14 +88,22 @@ __device__ __forceinline__ float gelu_f(float x) {
 }
 
 // tanh-form GELU from the table of linear pieces in LDS (tab: the
-// (slope, intercept) pairs; the pieces interpolate the function with their
-// error centred, at most 5e-5 away from it, below the bf16 rounding of the
-// result).  Arguments beyond [-8, 8) use the outermost piece: 0 below, x
-// above.
+// (slope, intercept) pairs; piece j spans a width 1/32 centred on
+// -8 + j/32 and interpolates the function with its error centred, at most
+// 5e-5 away from it, below the bf16 rounding of the result).  Arguments
+// beyond the table use the outermost piece: 0 below, x above.  The piece
+// index is round(32 (x + 8)): one FMA adds 2^23 as well, which leaves that
+// integer in the low mantissa bits of the rounded sum (x 32 is exact, so
+// the FMA rounds once; a tie takes the even piece, and both neighbours
+// agree there to 5e-5), and the clamped bit pattern shifted by 3 is the
+// byte offset of the piece plus a constant that one shift-and-add removes.
 __device__ __forceinline__ float gelu_tab(float x, const float2 *tab) {
-  const float t = __builtin_amdgcn_fmed3f(fmaf(x, (float)kGeluPerUnit, 8.0f * kGeluPerUnit), 0.0f,
-                                          (float)(kGeluSegs - 1));
-  const float2 c = tab[(int)t];
+  constexpr float kTwo23 = 8388608.0f;
+  static_assert(8.0f * kGeluPerUnit + kTwo23 == 8388864.0f, "the offset must be exact at 2^23");
+  const float t = __builtin_amdgcn_fmed3f(fmaf(x, (float)kGeluPerUnit, 8.0f * kGeluPerUnit + kTwo23), kTwo23,
+                                          kTwo23 + (float)(kGeluSegs - 1));
+  const uint32_t off = (__float_as_uint(t) << 3) - (__float_as_uint(kTwo23) << 3);
+  const float2 c = *(const float2 *)((const char *)tab + off);
   return fmaf(c.x, x, c.y);
 }
 
