@@ -353,7 +353,7 @@ lbm_status lbm_set_merge_limit(lbm_grid *g, int64_t max_blocks);
 /* Residency cap of the stepping kernels (a tuning knob; results are bit for
  * bit the same either way).  Each 256-thread workgroup of the block kernels
  * (every kernel of lbm_step except the closure's and the multires jump and
- * merged-level kernels, which hold LDS of their own) requests LDS it never
+ * merged-level kernels, which always run uncapped) requests LDS it never
  * touches, (LDS per CU) / wg_per_cu bytes rounded down to 1 KiB, so that at
  * most wg_per_cu workgroups (4 waves each) sit on one compute unit.  The
  * HBM bytes stay the same; fewer requests in flight raise the rate at which

@@ -704,10 +704,9 @@ static int32_t auto_residency(const Launch &x, int32_t storage, int32_t q) {
 }
 
 static uint32_t residency_lds(const lbm_grid *g, const Launch &x) {
-  // the multires jump and merged-level kernels hold 10-20 KiB of LDS of
-  // their own (the compiler keeps their per-lane table of source buffers
-  // there): a request sized for the whole CU would not fit beside it, so
-  // they are never capped
+  // the multires jump and merged-level kernels run uncapped: they serve
+  // levels too small to fill the chip (the merged forms by construction),
+  // where every cap measured slower
   if (x.kind == kKernelJump || x.kind == kKernelLevelMerged || x.kind == kKernelLevelPair) return 0;
   const int32_t w = g->residency >= 0 ? g->residency : auto_residency(x, g->desc.storage, g->q);
   return g->lds_of[w < 0 ? 0 : (w > 8 ? 8 : w)];

@@ -381,25 +381,25 @@ __global__ __launch_bounds__(256) void k_block_collide(StepArgs a, int32_t g0, i
 // of 8 such entries whose mean is taken (coalescence onto the 2x2x2
 // footprint of a coarse voxel).  Explosion, re-entry and coalescence are all
 // gathers, so no atomics and no second pass are needed.
-// The five source buffers come in as wave-uniform values held in scalar
-// registers, and the per-lane choice is a chain of selects between them (an
-// indexed read of the argument block would add a dependent memory load to
-// every gather).
-template <class T>
-struct MrBases {
-  const __attribute__((address_space(1))) T *p[5];  // global memory
-};
-
+// The five source buffers come in as wave-uniform 64-bit values held in
+// scalar registers, and the per-lane choice is a chain of selects between
+// them (an indexed read of the argument block, or of a table the compiler
+// builds in LDS when the bases sit in an array or structure, would add a
+// dependent memory load to every gather: that form measured 20-35% slower
+// on the sphere grids).
 template <class ST>
-__device__ __forceinline__ float mr_fetch(const MrBases<typename ST::T> &mb, uint32_t e, int plane, int opp_plane) {
+__device__ __forceinline__ float mr_fetch(uint64_t p0, uint64_t p1, uint64_t p2, uint64_t p3, uint64_t p4,
+                                          uint32_t e, int plane, int opp_plane) {
   using T = typename ST::T;
   const uint32_t tag = e >> 29;
   const uint32_t slot = e & ((1u << 28) - 1u);
   const int pl = (e >> 28) & 1u ? opp_plane : plane;
-  const __attribute__((address_space(1))) T *base = mb.p[0];
-#pragma unroll
-  for (int t = 1; t < 5; ++t) base = tag == (uint32_t)t ? mb.p[t] : base;
-  return ST::decode(base[pidx(pl, slot)]);
+  uint64_t base = p0;
+  base = tag == 1u ? p1 : base;
+  base = tag == 2u ? p2 : base;
+  base = tag == 3u ? p3 : base;
+  base = tag == 4u ? p4 : base;
+  return ST::decode(((const __attribute__((address_space(1))) T *)base)[pidx(pl, slot)]);
 }
 
 constexpr int kJumpGroup = 4;  // directions whose coalescence lists load together
@@ -412,9 +412,11 @@ __device__ __forceinline__ void mr_jump_block(const StepArgs &a, const MrArgs &m
   T *__restrict__ dst = (T *)a.dst;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
   const uint32_t *tab = m.jtab + ((size_t)b * 2 + m.phase) * Q * 64 + lane;
-  MrBases<T> mb;
-#pragma unroll
-  for (int t = 0; t < 5; ++t) mb.p[t] = (const __attribute__((address_space(1))) T *)(const T *)m.src[t];
+  // the five bases as plain 64-bit values (a structure or array of them
+  // held in memory lets the compiler turn the selects into a per-lane table
+  // in LDS, a dependent LDS read in front of every gather)
+  const uint64_t p0 = (uint64_t)m.src[0], p1 = (uint64_t)m.src[1], p2 = (uint64_t)m.src[2],
+                 p3 = (uint64_t)m.src[3], p4 = (uint64_t)m.src[4];
   // three rounds of independent loads: the table entries, the direct
   // gathers, then the coalescence lists
   uint32_t e[Q];
@@ -425,7 +427,7 @@ __device__ __forceinline__ void mr_jump_block(const StepArgs &a, const MrArgs &m
     constexpr int i = decltype(ic)::value;
     // a lane with a list entry reads slot 0 of the first buffer here (a
     // valid address) and takes its list mean below
-    h[i] = mr_fetch<ST>(mb, (e[i] >> 29) == 7u ? 0u : e[i], i, kOpp[i]);
+    h[i] = mr_fetch<ST>(p0, p1, p2, p3, p4, (e[i] >> 29) == 7u ? 0u : e[i], i, kOpp[i]);
   });
   // Coalescence lists, kJumpGroup directions at a time: every lane of a
   // group with a list in the wave loads list entries (lanes without one
@@ -456,7 +458,7 @@ __device__ __forceinline__ void mr_jump_block(const StepArgs &a, const MrArgs &m
 #pragma unroll
       for (int k = 0; k < G; ++k)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[k][j] = mr_fetch<ST>(mb, ent[k][j], i0 + k, kOpp[i0 + k]);
+        for (int j = 0; j < 8; ++j) v[k][j] = mr_fetch<ST>(p0, p1, p2, p3, p4, ent[k][j], i0 + k, kOpp[i0 + k]);
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         float sum = v[k][0];
