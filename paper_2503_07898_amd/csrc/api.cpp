@@ -689,14 +689,14 @@ static lbm_status size_residency(lbm_grid *g) {
 
 // Workgroups per CU of each block kernel under LBM_RESIDENCY_AUTO (0: no
 // cap), from sweeps of every kernel kind, storage and lattice on MI355X.
-// Launches of fewer than 65536 blocks are not capped: with under 64
+// Launches of fewer than 16384 blocks are not capped: with under 16
 // workgroups per CU they need every wave slot for loads in flight.
 static int32_t auto_residency(const Launch &x, int32_t storage, int32_t q) {
-  if (x.count < 65536) return 0;
+  if (x.count < 16384) return 0;
   const bool f32 = storage == LBM_F32, q19 = q == 19;
   switch (x.kind) {
     case kKernelFull: return f32 ? 5 : (q19 ? 6 : 5);
-    case kKernelMasked: return f32 ? 5 : (q19 ? 7 : 0);
+    case kKernelMasked: return f32 ? 5 : (q19 ? 6 : 0);
     case kKernelInteriorBits: return q19 ? (f32 ? 5 : 7) : 0;
     case kKernelBoundary: return q19 ? (f32 ? 6 : 7) : 0;
     default: return 0;

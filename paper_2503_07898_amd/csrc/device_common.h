@@ -439,12 +439,24 @@ __device__ __forceinline__ void regularized_face(float (&h)[Q], uint32_t unknown
 }
 
 // ------------------------------------------------------------ utilities ---
-// Workgroup id remap so that consecutive logical workgroups (consecutive
-// Morton-ordered blocks) run on the same XCD: the hardware deals workgroup k
-// to XCD k % 8, so XCD x receives the x-th contiguous share of the range.
-__device__ __forceinline__ int xcd_remap(int k, int nwg) {
-  const int per = nwg >> 3, rem = nwg & 7, x = k & 7, i = k >> 3;
-  return x * per + (x < rem ? x : rem) + i;
+// Workgroup order of the block kernels.  The hardware deals workgroup k to
+// XCD k % 8; the logical workgroups (4 consecutive Morton-ordered blocks
+// each) are cut into chunks of kXcdChunk, and XCD x takes chunks x, x + 8,
+// x + 16, ... in turn.  A chunk (32 blocks) stays on one XCD and its L2,
+// and at any moment the eight XCDs work on neighbouring chunks, so the rows
+// that blocks pull across chunk faces are fetched once into the shared
+// Infinity Cache for all of them and the DRAM traffic of the chip covers
+// one compact region.  (Contiguous eighths of the range per XCD measured
+// 6% slower on the FP32 interior kernel, chunks of 4 or 32 workgroups 2%.)
+// The grid is padded to whole rounds of 8 chunks (xcd_grid); the padding
+// workgroups map past the last block and exit.
+constexpr int kXcdChunk = 8;
+__host__ __device__ constexpr int xcd_grid(int nwg) {
+  return (nwg + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);
+}
+__device__ __forceinline__ int xcd_remap(int k) {
+  const int x = k & 7, i = k >> 3;
+  return ((i / kXcdChunk) * 8 + x) * kXcdChunk + i % kXcdChunk;
 }
 
 }  // inline namespace

@@ -103,7 +103,7 @@ __device__ __forceinline__ void interior_block(const StepArgs &a, int b) {
 
 template <class ST, int COLL, bool MASKED, bool FUSED>
 __global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, int32_t n) {
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wg = xcd_remap(blockIdx.x);
   const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
   if (b >= g0 + n) return;
   interior_block<ST, COLL, MASKED, FUSED>(a, b);
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_block_interior(StepArgs a, int32_t g0, 
 // blocks that the memory-based layout separates as "full").
 template <class ST, int COLL>
 __global__ __launch_bounds__(256) void k_block_interior_bits(StepArgs a, int32_t g0, int32_t n) {
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wg = xcd_remap(blockIdx.x);
   const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
   if (b >= g0 + n) return;
   if ((a.bbits[b >> 5] >> (b & 31)) & 1u) return;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
   using T = typename ST::T;
   __shared__ __attribute__((aligned(16))) __bf16 wl[kWStageElems];
   stage_weights(wl, (const __bf16 *)a.mlp_w);
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wg = xcd_remap(blockIdx.x);
   const int wave = threadIdx.x >> 6;
   const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + wave);
   if (b >= g0 + n) return;
@@ -318,7 +318,7 @@ __device__ __forceinline__ void boundary_block(const StepArgs &a, int b) {
 
 template <class ST, int COLL, bool FUSED>
 __global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, int32_t n) {
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wg = xcd_remap(blockIdx.x);
   const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
   if (b >= g0 + n) return;
   boundary_block<ST, COLL, FUSED, false>(a, b);
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_block_boundary(StepArgs a, int32_t g0, 
 // Bitmask-based grouping: visits every block, keeps the boundary ones.
 template <class ST, int COLL>
 __global__ __launch_bounds__(256) void k_block_boundary_bits(StepArgs a, int32_t g0, int32_t n) {
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wg = xcd_remap(blockIdx.x);
   const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
   if (b >= g0 + n) return;
   if (!((a.bbits[b >> 5] >> (b & 31)) & 1u)) return;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void k_block_boundary_bits(StepArgs a, int32_t
 template <class ST, int COLL, bool HEAVY>
 __global__ __launch_bounds__(256) void k_block_collide(StepArgs a, int32_t g0, int32_t n) {
   using T = typename ST::T;
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wg = xcd_remap(blockIdx.x);
   const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
   if (b >= g0 + n) return;
   const int lane = threadIdx.x & 63;
@@ -475,7 +475,7 @@ __device__ __forceinline__ void mr_jump_block(const StepArgs &a, const MrArgs &m
 
 template <class ST, int COLL, bool FUSED>
 __global__ __launch_bounds__(256) void k_mr_jump(StepArgs a, MrArgs m, int32_t g0, int32_t n) {
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wg = xcd_remap(blockIdx.x);
   const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + (int)(threadIdx.x >> 6));
   if (b >= g0 + n) return;
   mr_jump_block<ST, COLL, FUSED>(a, m, b);
@@ -661,7 +661,7 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
   }
   const int32_t g0 = L.first, n = L.count;
   if (n <= 0) return hipSuccess;
-  const dim3 grd((n + 3) / 4), blk(256);
+  const dim3 grd(xcd_grid((n + 3) / 4)), blk(256);  // the block kernels' order (xcd_remap)
   const bool f = L.fused != 0;
   switch (L.kind) {
     case kKernelFull:
@@ -726,7 +726,7 @@ template <class ST>
 static hipError_t launch_mlp(const Launch &L, hipStream_t s) {
   const int32_t g0 = L.first, n = L.count;
   if (n <= 0) return hipSuccess;
-  const dim3 grd((n + 3) / 4), blk(256);
+  const dim3 grd(xcd_grid((n + 3) / 4)), blk(256);
   if (L.kind == kKernelFull) hipLaunchKernelGGL((k_block_interior_mlp<ST, false>), grd, blk, 0, s, L.args, g0, n);
   else hipLaunchKernelGGL((k_block_interior_mlp<ST, true>), grd, blk, 0, s, L.args, g0, n);
   return hipGetLastError();

@@ -305,6 +305,31 @@ def test_multires_merged_level_updates():
     g.close()
 
 
+def test_xcd_order_covers_every_block_once():
+    """The block kernels' workgroup order: logical workgroup
+    ((i / C) * 8 + k % 8) * C + i % C for hardware workgroup k (i = k / 8,
+    chunks of C = 8), over a grid padded to whole rounds of 8 C; restated
+    here, it must reach every logical workgroup exactly once and send the
+    padding past the end, for any block count."""
+    C = 8
+
+    def remap(k):
+        x, i = k & 7, k >> 3
+        return ((i // C) * 8 + x) * C + i % C
+
+    for nblocks in (1, 3, 4, 5, 63, 64, 255, 256, 257, 1000, 2474, 23816, 70115):
+        nwg = (nblocks + 3) // 4
+        grid = (nwg + 8 * C - 1) // (8 * C) * (8 * C)
+        v = np.array([remap(k) for k in range(grid)])
+        assert sorted(v) == list(range(grid))
+        assert np.array_equal(np.sort(v[v < nwg]), np.arange(nwg))
+        # hardware workgroup k runs on XCD k % 8: a chunk of C logical
+        # workgroups stays on one XCD
+        xcd = np.empty(grid, int)
+        xcd[v] = np.arange(grid) % 8
+        assert np.all(xcd.reshape(-1, C) == xcd.reshape(-1, C)[:, :1])
+
+
 def test_residency_setting_range():
     """lbm_set_residency takes LBM_RESIDENCY_AUTO (-1), 0 (no cap) or 1..8
     workgroups per CU, in any grid state, and rejects everything else."""
