@@ -442,15 +442,17 @@ __device__ __forceinline__ void regularized_face(float (&h)[Q], uint32_t unknown
 // Workgroup order of the block kernels.  The hardware deals workgroup k to
 // XCD k % 8; the logical workgroups (4 consecutive Morton-ordered blocks
 // each) are cut into chunks of kXcdChunk, and XCD x takes chunks x, x + 8,
-// x + 16, ... in turn.  A chunk (32 blocks) stays on one XCD and its L2,
+// x + 16, ... in turn.  A chunk (64 blocks, a 4x4x4-block Morton cube of a
+// dense grid) stays on one XCD and its L2,
 // and at any moment the eight XCDs work on neighbouring chunks, so the rows
 // that blocks pull across chunk faces are fetched once into the shared
 // Infinity Cache for all of them and the DRAM traffic of the chip covers
 // one compact region.  (Contiguous eighths of the range per XCD measured
-// 6% slower on the FP32 interior kernel, chunks of 4 or 32 workgroups 2%.)
+// 6% slower on the FP32 interior kernel; chunks of 4, 8 and 32 workgroups
+// 1-2%, 0.5-1% and 0-3% slower over the whole steps.)
 // The grid is padded to whole rounds of 8 chunks (xcd_grid); the padding
 // workgroups map past the last block and exit.
-constexpr int kXcdChunk = 8;
+constexpr int kXcdChunk = 16;
 __host__ __device__ constexpr int xcd_grid(int nwg) {
   return (nwg + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);
 }

@@ -308,10 +308,10 @@ def test_multires_merged_level_updates():
 def test_xcd_order_covers_every_block_once():
     """The block kernels' workgroup order: logical workgroup
     ((i / C) * 8 + k % 8) * C + i % C for hardware workgroup k (i = k / 8,
-    chunks of C = 8), over a grid padded to whole rounds of 8 C; restated
+    chunks of C = 16), over a grid padded to whole rounds of 8 C; restated
     here, it must reach every logical workgroup exactly once and send the
     padding past the end, for any block count."""
-    C = 8
+    C = 16
 
     def remap(k):
         x, i = k & 7, k >> 3
