@@ -521,7 +521,9 @@ __device__ __forceinline__ void level_merged_body(const StepArgs &a, const MrArg
 template <class ST, int COLL, bool FUSED, bool JFUSED = FUSED>
 __global__ __launch_bounds__(256) void k_level_merged(StepArgs a, MrArgs m, int32_t nj, int32_t nbd, int32_t nm,
                                                       int32_t nf) {
-  level_merged_body<ST, COLL, FUSED, JFUSED>(a, m, nj, nbd, nm, nf, (int)blockIdx.x);
+  // the chunked XCD order over all groups; padding workgroups land past the
+  // last full block and exit
+  level_merged_body<ST, COLL, FUSED, JFUSED>(a, m, nj, nbd, nm, nf, xcd_remap(blockIdx.x));
 }
 
 // Two merged level updates with no buffer in common between one's writes
@@ -533,7 +535,7 @@ __global__ __launch_bounds__(256) void k_level_merged(StepArgs a, MrArgs m, int3
 template <class ST, int COLL>
 __global__ __launch_bounds__(256) void k_level_pair(StepArgs a0, MrArgs m0, int4 c0, StepArgs a1, MrArgs m1,
                                                     int4 c1) {
-  const int k = (int)blockIdx.x;
+  const int k = xcd_remap(blockIdx.x);  // padding lands past the second update's last block
   const int w0 = ((c0.x + 3) >> 2) + ((c0.y + 3) >> 2) + ((c0.z + 3) >> 2) + ((c0.w + 3) >> 2);
   if (k < w0) level_merged_body<ST, COLL, true, true>(a0, m0, c0.x, c0.y, c0.z, c0.w, k);
   else level_merged_body<ST, COLL, true, true>(a1, m1, c1.x, c1.y, c1.z, c1.w, k - w0);
@@ -683,7 +685,7 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
       break;
     case kKernelLevelMerged: {
       const int32_t *c = L.gcount;
-      const dim3 gm((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4);
+      const dim3 gm(xcd_grid((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4));
       if (g0 != 0 || c[0] + c[1] + c[2] + c[3] != n) return hipErrorInvalidValue;
       if (L.fused == 2)  // uniform groups fused, jump group streamed only
         hipLaunchKernelGGL((k_level_merged<ST, COLL, true, false>), gm, blk, 0, s, L.args, L.mr, c[0], c[1], c[2],
@@ -695,8 +697,8 @@ static hipError_t launch_t(const Launch &L, hipStream_t s) {
     }
     case kKernelLevelPair: {
       const int32_t *c = L.gcount, *d = L.gcount2;
-      const dim3 gm((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4 + (d[0] + 3) / 4 +
-                    (d[1] + 3) / 4 + (d[2] + 3) / 4 + (d[3] + 3) / 4);
+      const dim3 gm(xcd_grid((c[0] + 3) / 4 + (c[1] + 3) / 4 + (c[2] + 3) / 4 + (c[3] + 3) / 4 + (d[0] + 3) / 4 +
+                    (d[1] + 3) / 4 + (d[2] + 3) / 4 + (d[3] + 3) / 4));
       if (!f) return hipErrorInvalidValue;
       hipLaunchKernelGGL((k_level_pair<ST, COLL>), gm, blk, 0, s, L.args, L.mr, make_int4(c[0], c[1], c[2], c[3]),
                          L.args2, L.mr2, make_int4(d[0], d[1], d[2], d[3]));
