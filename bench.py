@@ -114,8 +114,11 @@ def source_hash() -> str:
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None if absent or taken on a different kernel source."""
+    """Bytes per launch of `kernel` that left the L2 (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy's readings) from the committed
+    rocprofv3 counter summary, or None if absent or taken on a different
+    kernel source.  An upper bound on the HBM bytes: reads that the Infinity
+    Cache serves count too, and no counter on this stack separates them."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(p) as fh:
