@@ -180,7 +180,12 @@ lbm_status lbm_init_equilibrium(lbm_grid *g, int32_t level, const double *rho_de
  * feeding the finer level) and coalescence (the finer level's streamed
  * values merging into coarse voxels, as the mean over the 2x2x2 footprint)
  * are gathers of the jump-group kernel; uniform blocks run the fused kernels
- * of the single-level grids. */
+ * of the single-level grids.  A step only launches kernels on `stream` (no
+ * allocation, memset or host synchronization after the first step of a
+ * grid), so it can be captured into a HIP graph: the graph holds the
+ * launches with the buffer roles they had, and the roles repeat every 2
+ * steps (dense, block-sparse) or every 3 coarse steps (multires), so a
+ * graph of a multiple of that many steps replays as further steps. */
 lbm_status lbm_step(lbm_grid *g, int32_t n_steps, void *stream);
 
 /* Density and velocity of every fluid voxel of `level` in canonical order,
