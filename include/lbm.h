@@ -372,6 +372,18 @@ lbm_status lbm_set_merge_limit(lbm_grid *g, int64_t max_blocks);
 #define LBM_RESIDENCY_AUTO (-1)
 lbm_status lbm_set_residency(lbm_grid *g, int32_t wg_per_cu);
 
+/* Pull addressing of the learned-closure kernel (a diagnostic knob; results
+ * are bit for bit the same either way).  While a population buffer spans at
+ * most 4 GiB the kernel forms each pull's address as a 32-bit byte offset
+ * over the buffer's start, built from wave-uniform neighbour deltas and
+ * per-lane face masks (fewer vector instructions in a kernel bound by their
+ * issue); larger buffers use 64-bit slot arithmetic.  wide = 1 forces the
+ * 64-bit form at any size, so that it can be checked against the 32-bit one
+ * on grids of every size; 0 (the default) restores the automatic choice.
+ * Any grid state; takes effect at the next launch.  Other values are
+ * LBM_ERR_INVALID_ARG. */
+lbm_status lbm_set_wide_addressing(lbm_grid *g, int32_t wide);
+
 /* n pre-collision population sets (FP32, unshifted, [n][19]: the values the
  * collision operator of the next step receives, pulled from the current
  * post-collision field with bounce-back) of fluid voxels drawn uniformly

@@ -101,6 +101,7 @@ struct lbm_grid {
   int64_t merge_max = kMergeMaxBlocks;  // multires: merged level updates up to this many blocks
   int32_t residency = LBM_RESIDENCY_AUTO;  // workgroups per CU of the block kernels, 0 = no cap
   bool lds_sized = false;                  // lds_of filled for the current device
+  int32_t wide = 0;                        // 1: 64-bit pull addressing whatever the buffer size
   uint32_t lds_of[9] = {};                 // LDS bytes per workgroup that cap residency at w
   LatticeLaunchers ops = LBM_LAUNCHERS_OF(lbm::k19);
   int32_t collision = LBM_BGK;
@@ -725,6 +726,7 @@ lbm_status lbm_step(lbm_grid *g, int32_t n, void *stream) {
     for (Launch x : p.launches) {
       x.args.mlp_judge = judge;
       x.lds = residency_lds(g, x);
+      x.wide = g->wide;
       hipError_t e = g->ops.one(x, g->desc.storage, coll_code(g), (hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "step launch");
     }
@@ -759,6 +761,7 @@ lbm_status lbm_launch_group(lbm_grid *g, int32_t k, void *stream) {
     if (lbm_status st = size_residency(g)) return st;
   }
   launches[k].lds = residency_lds(g, launches[k]);
+  launches[k].wide = g->wide;
   hipError_t e = g->ops.one(launches[k], g->desc.storage, coll_code(g), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "launch_group");
   return LBM_OK;
@@ -1122,6 +1125,13 @@ lbm_status lbm_set_residency(lbm_grid *g, int32_t wg_per_cu) {
   if (wg_per_cu < LBM_RESIDENCY_AUTO || wg_per_cu > 8)
     return fail(LBM_ERR_INVALID_ARG, "workgroups per CU must be LBM_RESIDENCY_AUTO or in 0..8");
   g->residency = wg_per_cu;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_wide_addressing(lbm_grid *g, int32_t wide) {
+  if (!g) return fail(LBM_ERR_INVALID_ARG, "null grid");
+  if (wide != 0 && wide != 1) return fail(LBM_ERR_INVALID_ARG, "wide must be 0 or 1");
+  g->wide = wide;
   return LBM_OK;
 }
 

@@ -71,6 +71,7 @@ struct Launch {
   int32_t first, count;   // block range of the launch
   uint32_t lds;           // dynamic LDS bytes the kernel never touches: requested only to cap the
                           // workgroups resident per CU (0: no cap)
+  int32_t wide;           // 1: 64-bit pull addressing in every kernel that has both forms
   int32_t gcount[4];      // kKernelLevelMerged: blocks of the jump, boundary, masked, full groups
   StepArgs args;
   MrArgs mr;

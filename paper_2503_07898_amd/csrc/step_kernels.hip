@@ -122,6 +122,61 @@ __global__ __launch_bounds__(256) void k_block_interior_bits(StepArgs a, int32_t
 }
 
 #ifndef LBM_Q27  // D3Q19 only
+// ------------------------------------------ 32-bit pull offsets (closure) --
+// For population buffers of at most 4 GiB the byte offset of every pull fits
+// in 32 bits, and it splits into a per-lane part that does not depend on the
+// direction and wave-uniform parts selected per lane by bit masks.  Lane v of
+// block b pulling direction I reads byte
+//   S (v + Q 64 b) + S (64 I - c_I.(1, 4, 16))
+//   + sum over the block faces the pull crosses of a uniform delta,
+// where crossing face x moves the source to block n_x (delta S Q 64 (n_x - b)
+// + 4 c_x S, the wrap of the x coordinate), and an edge pull adds a second
+// order term so that the sum lands in the edge neighbour's block.  All of it
+// is taken modulo 2^32, and the true offset is below 2^32.  One AND and one
+// add per crossed face replace the 64-bit slot arithmetic, which keeps the
+// vector-instruction count of the issue-bound closure kernel down.
+struct LaneFaces {
+  uint32_t x0, x3, y0, y3, z0, z3;  // all ones where the lane sits on that face of its block
+  template <int C> __device__ __forceinline__ uint32_t x() const { return C > 0 ? x0 : x3; }
+  template <int C> __device__ __forceinline__ uint32_t y() const { return C > 0 ? y0 : y3; }
+  template <int C> __device__ __forceinline__ uint32_t z() const { return C > 0 ? z0 : z3; }
+};
+
+__device__ __forceinline__ LaneFaces lane_faces(int lane) {
+  const auto all = [](bool c) { return c ? ~0u : 0u; };
+  return {all((lane & 3) == 0), all((lane & 3) == 3), all((lane & 12) == 0),
+          all((lane & 12) == 12), all(lane < 16), all(lane >= 48)};
+}
+
+// byte offset of lane's pull source in direction I; `base` = S (lane + Q 64 own)
+template <int I, int S>
+__device__ __forceinline__ uint32_t pull_off32(uint32_t base, const LaneFaces &lf, int own,
+                                               const int32_t (&nbv)[kNbr]) {
+  constexpr int cx = kCx[I], cy = kCy[I], cz = kCz[I];
+  static_assert(!(cx != 0 && cy != 0 && cz != 0), "D3Q19 has no corner directions");
+  constexpr uint32_t QS = (uint32_t)(Q * 64 * S);
+  const uint32_t own_q = (uint32_t)own * QS;
+  const auto delta = [&](int d, int wrap) { return (uint32_t)nbv[d - 1] * QS - own_q + (uint32_t)(wrap * S); };
+  uint32_t off = base + (uint32_t)((64 * I - (cx + 4 * cy + 16 * cz)) * S);
+  uint32_t dx = 0, dy = 0, dz = 0;
+  if constexpr (cx != 0) {
+    dx = delta(dir_of(-cx, 0, 0), 4 * cx);
+    off += lf.x<cx>() & dx;
+  }
+  if constexpr (cy != 0) {
+    dy = delta(dir_of(0, -cy, 0), 16 * cy);
+    off += lf.y<cy>() & dy;
+  }
+  if constexpr (cz != 0) {
+    dz = delta(dir_of(0, 0, -cz), 64 * cz);
+    off += lf.z<cz>() & dz;
+  }
+  if constexpr (cx != 0 && cy != 0) off += (lf.x<cx>() & lf.y<cy>()) & (delta(dir_of(-cx, -cy, 0), 4 * cx + 16 * cy) - dx - dy);
+  if constexpr (cx != 0 && cz != 0) off += (lf.x<cx>() & lf.z<cz>()) & (delta(dir_of(-cx, 0, -cz), 4 * cx + 64 * cz) - dx - dz);
+  if constexpr (cy != 0 && cz != 0) off += (lf.y<cy>() & lf.z<cz>()) & (delta(dir_of(0, -cy, -cz), 16 * cy + 64 * cz) - dy - dz);
+  return off;
+}
+
 // ------------------------------------------ interior kernel, learned closure --
 // Same gather as k_block_interior; the collision evaluates the closure
 // network for the wave's 64 voxels on the matrix cores, projects its output
@@ -133,7 +188,8 @@ __global__ __launch_bounds__(256) void k_block_interior_bits(StepArgs a, int32_t
 // (at most 168 registers): the network's accumulators then stay in ordinary
 // registers (no accumulator-register reads) and a third wave hides more of
 // the LDS and matrix-core latency.
-template <class ST, bool MASKED>
+// NARROW: population buffers of at most 4 GiB (32-bit pull offsets).
+template <class ST, bool MASKED, bool NARROW>
 __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32_t g0, int32_t n) {
   using T = typename ST::T;
   __shared__ __attribute__((aligned(16))) __bf16 wl[kWStageElems];
@@ -158,19 +214,35 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
   // of three waves per SIMD this keeps the 19 loads of 16-bit storage in
   // flight together instead of one converted value at a time
   T raw[Q];
-  raw[0] = src[pidx(0, own_slot)];
-  static_for<1, Q>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    uint32_t slot = pull_slot<i>(lane, b, nbv);
-    uint32_t plane = i;
-    if constexpr (MASKED) {
-      if ((bm[i - 1] >> lane) & 1ull) {
-        slot = own_slot;
-        plane = kOpp[i];
+  if constexpr (NARROW) {
+    constexpr int S = (int)sizeof(T);
+    const LaneFaces lf = lane_faces(lane);
+    const uint32_t base = (uint32_t)lane * S + (uint32_t)b * (uint32_t)(Q * 64 * S);
+    const char *src8 = (const char *)src;
+    raw[0] = *(const T *)(src8 + base);
+    static_for<1, Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      uint32_t off = pull_off32<i, S>(base, lf, b, nbv);
+      if constexpr (MASKED) {
+        if ((bm[i - 1] >> lane) & 1ull) off = base + (uint32_t)(kOpp[i] * 64 * S);
       }
-    }
-    raw[i] = src[pidx(plane, slot)];
-  });
+      raw[i] = *(const T *)(src8 + off);
+    });
+  } else {
+    raw[0] = src[pidx(0, own_slot)];
+    static_for<1, Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      uint32_t slot = pull_slot<i>(lane, b, nbv);
+      uint32_t plane = i;
+      if constexpr (MASKED) {
+        if ((bm[i - 1] >> lane) & 1ull) {
+          slot = own_slot;
+          plane = kOpp[i];
+        }
+      }
+      raw[i] = src[pidx(plane, slot)];
+    });
+  }
   float h[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) h[i] = ST::decode(raw[i]);
@@ -233,7 +305,10 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     h[i] = fmaf(r, y[i], heq[i]);
-    negative = negative || (weight_f(i) + h[i] < 0.0f);
+    // w_i + h_i < 0 in FP32 exactly when h_i < -w_i: the rounded sum keeps
+    // the sign of the exact one, which is a multiple of h_i's unit in the
+    // last place and so never underflows
+    negative = negative || (h[i] < -weight_f(i));
   }
   const bool fb = fluid && (out_of_range || negative || off);
   if (fb) {
@@ -246,8 +321,9 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
   }
   const uint64_t bal = __ballot(fb);
   if (lane == 0 && bal) atomicAdd(a.mlp_fallbacks, (unsigned long long)__popcll(bal));
+  T *dstb = dst + (size_t)b * (Q * 64);  // the block's rows, from a wave-uniform base
 #pragma unroll
-  for (int i = 0; i < Q; ++i) ST::store(dst, pidx(i, own_slot), h[i]);
+  for (int i = 0; i < Q; ++i) ST::store(dstb, (size_t)(i * 64 + lane), h[i]);
 }
 
 #endif  // LBM_Q27
@@ -729,8 +805,15 @@ static hipError_t launch_mlp(const Launch &L, hipStream_t s) {
   const int32_t g0 = L.first, n = L.count;
   if (n <= 0) return hipSuccess;
   const dim3 grd(xcd_grid((n + 3) / 4)), blk(256);
-  if (L.kind == kKernelFull) hipLaunchKernelGGL((k_block_interior_mlp<ST, false>), grd, blk, 0, s, L.args, g0, n);
-  else hipLaunchKernelGGL((k_block_interior_mlp<ST, true>), grd, blk, 0, s, L.args, g0, n);
+  // 32-bit pull offsets while a population buffer spans at most 4 GiB
+  const bool narrow = (uint64_t)L.args.S * Q * sizeof(typename ST::T) <= (1ull << 32) && !L.wide;
+  if (L.kind == kKernelFull) {
+    if (narrow) hipLaunchKernelGGL((k_block_interior_mlp<ST, false, true>), grd, blk, 0, s, L.args, g0, n);
+    else hipLaunchKernelGGL((k_block_interior_mlp<ST, false, false>), grd, blk, 0, s, L.args, g0, n);
+  } else {
+    if (narrow) hipLaunchKernelGGL((k_block_interior_mlp<ST, true, true>), grd, blk, 0, s, L.args, g0, n);
+    else hipLaunchKernelGGL((k_block_interior_mlp<ST, true, false>), grd, blk, 0, s, L.args, g0, n);
+  }
   return hipGetLastError();
 }
 #endif

@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
             "lbm_set_collision": ([vp, i32, vp], i32),
             "lbm_set_merge_limit": ([vp, i64], i32),
             "lbm_set_residency": ([vp, i32], i32),
+            "lbm_set_wide_addressing": ([vp, i32], i32),
             "lbm_check": ([vp, vp], i32),
             "lbm_sample_populations": ([vp, i32, ctypes.c_uint64, i64, vp, vp], i32),
             "lbm_grid_destroy": ([vp], i32),
@@ -298,6 +299,10 @@ def lbm_set_residency(g, wg_per_cu: int) -> None:
     check(lib().lbm_set_residency(g, int(wg_per_cu)))
 
 
+def lbm_set_wide_addressing(g, wide: int) -> None:
+    check(lib().lbm_set_wide_addressing(g, int(wide)))
+
+
 def lbm_sample_populations(g, level: int, seed: int, n: int, f_ptr: int, stream=None) -> None:
     check(lib().lbm_sample_populations(g, int(level), ctypes.c_uint64(seed), int(n), f_ptr, _stream_ptr(stream)))
 
@@ -442,6 +447,11 @@ class Grid:
         """Caps the stepping kernels at wg_per_cu resident workgroups per CU
         (0: no cap, RESIDENCY_AUTO: the measured per-kernel default)."""
         lbm_set_residency(self.h, wg_per_cu)
+
+    def set_wide_addressing(self, wide: bool) -> None:
+        """Forces the closure kernel's 64-bit pull addressing (True) or
+        restores the automatic 32-bit form for buffers up to 4 GiB (False)."""
+        lbm_set_wide_addressing(self.h, 1 if wide else 0)
 
     def sample(self, seed: int, n: int, level: int = 0):
         import torch

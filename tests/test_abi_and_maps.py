@@ -342,6 +342,18 @@ def test_residency_setting_range():
     g.close()
 
 
+def test_wide_addressing_setting():
+    """lbm_set_wide_addressing takes 0 or 1 in any grid state and rejects
+    everything else."""
+    g = lbm.Grid(16, 16, 16, device="cpu")
+    g.set_wide_addressing(True)
+    g.set_wide_addressing(False)
+    for w in (-1, 2):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_set_wide_addressing(g.h, w)
+    g.close()
+
+
 @pytest.mark.parametrize("case", [0, 1, 4])
 @pytest.mark.parametrize("grouped", [True, False])
 def test_index_maps_d3q27(orc, case, grouped):

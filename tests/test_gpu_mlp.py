@@ -301,3 +301,40 @@ def test_closure_in_solver(orc):
     assert fbs["mlp"] <= fbs["untrained"]
     m.close()
     untrained.close()
+
+
+@pytest.mark.parametrize("case", ["taylor_green", "cavity"])
+@pytest.mark.parametrize("storage", [lbm.F32, lbm.F16_SHIFTED, lbm.BF16_SHIFTED])
+def test_closure_addressing_forms_bitwise(case, storage):
+    """The closure kernel's 32-bit pull offsets (buffers up to 4 GiB) and its
+    64-bit slot arithmetic (larger buffers, forced here) give the same
+    populations bit for bit and the same fallback count: periodic
+    Taylor-Green 32^3 (full blocks only) and a lid-driven cavity 32^3 (full,
+    masked and boundary groups), trained weights, judge on, 4 steps."""
+    from paper_2503_07898_amd import cases, train_closure
+    w = train_closure.load()
+    if w is None:
+        pytest.skip("no trained closure weights in the package")
+    net = lbm.Mlp()
+    net.set_params(w[0])
+    net.set_standardization(w[1])
+    net.set_judge(0.01)
+    out = {}
+    for wide in (False, True):
+        _say(f"  closure addressing: {case} storage={storage} wide={wide}")
+        if case == "cavity":
+            g = cases.cavity(n=32, storage=storage, tau=0.52)
+        else:
+            g = cases.taylor_green(n=32, re=400.0, storage=storage)
+        g.set_collision(lbm.MLP, net)
+        g.set_wide_addressing(wide)
+        net.fallbacks(reset=True)
+        g.step(4)
+        torch.cuda.synchronize()
+        out[wide] = (g.populations().cpu().numpy(), net.fallbacks())
+        g.close()
+    net.close()
+    a, b = out[False], out[True]
+    assert np.isfinite(a[0]).all()
+    assert np.array_equal(a[0].view(np.uint8), b[0].view(np.uint8))
+    assert a[1] == b[1]
