@@ -295,7 +295,7 @@ def main(argv=None) -> int:
                     "mfma_frac": round(ups * MLP_MFMA_FLOPS / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
                 # the binding resource of the closure: vector-instruction issue
                 # (one wave per block), from the counted instructions per wave
-                kname = f"lbm::k19::k_block_interior_mlp<lbm::k19::{STORE_NAME[interior]}, false>"
+                kname = f"lbm::k19::k_block_interior_mlp<lbm::k19::{STORE_NAME[interior]}, false, true>"
                 vpw = measured_valu(kname)
                 il = arms[name]["interior_launch"]
                 il["valu_insts_per_wave"] = vpw

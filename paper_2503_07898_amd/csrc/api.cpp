@@ -66,7 +66,7 @@ struct lbm_mlp {
   float judge = 0.01f;  // relative L2 tolerance of the closure against the regularized f1
   size_t off_params = 0, off_m = 0, off_v = 0, off_grads = 0, off_w = 0, off_bias = 0, off_stdz = 0,
          off_fb = 0, off_save = 0, off_dyt = 0, off_dz1 = 0, off_dz2 = 0, off_partial = 0, off_loss = 0,
-         off_gpartial = 0;
+         off_gpartial = 0, off_s2 = 0;
   char *ws = nullptr;
   MlpBuffers B{};
 };
@@ -159,6 +159,7 @@ StepArgs level_args(const lbm_grid *g, const LevelRT &r) {
     a.mlp_w = g->mlp->B.wpacked;
     a.mlp_bias = g->mlp->B.bias;
     a.mlp_stdz = g->mlp->B.stdz;
+    a.mlp_s2 = g->mlp->B.s2;
     a.mlp_fallbacks = g->mlp->B.fallbacks;
     a.mlp_judge = g->mlp->judge;
   }
@@ -913,6 +914,7 @@ lbm_status lbm_mlp_create(lbm_mlp **out, size_t *bytes) {
   take(m->off_w, kWPackedElems * 2 + kGeluTabBytes);  // packed weights, then the GELU table
   take(m->off_bias, kBiasFloats * 4);
   take(m->off_stdz, kStdFloats * 4);
+  take(m->off_s2, 4);
   take(m->off_fb, 256);
   take(m->off_save, (size_t)bmax * kSaveFloats * 4);
   take(m->off_dyt, (size_t)bmax * Q * 4);
@@ -942,6 +944,7 @@ lbm_status lbm_mlp_bind(lbm_mlp *m, void *dev, size_t bytes, void *stream) {
   B.wpacked = m->ws + m->off_w;
   B.bias = (float *)(m->ws + m->off_bias);
   B.stdz = (float *)(m->ws + m->off_stdz);
+  B.s2 = (float *)(m->ws + m->off_s2);
   B.fallbacks = (unsigned long long *)(m->ws + m->off_fb);
   B.save = (float *)(m->ws + m->off_save);
   B.dyt = (float *)(m->ws + m->off_dyt);
@@ -960,6 +963,7 @@ lbm_status lbm_mlp_bind(lbm_mlp *m, void *dev, size_t bytes, void *stream) {
   if (!e) e = hipMemcpyAsync(B.adam_m, zeros.data(), kMlpParams * 4, hipMemcpyHostToDevice, s);
   if (!e) e = hipMemcpyAsync(B.adam_v, zeros.data(), kMlpParams * 4, hipMemcpyHostToDevice, s);
   if (!e) e = hipMemcpyAsync(B.stdz, stdz.data(), kStdFloats * 4, hipMemcpyHostToDevice, s);
+  if (!e) e = mlp_derive(B, s);
   if (!e) e = hipMemcpyAsync(B.fallbacks, zero_count, sizeof zero_count, hipMemcpyHostToDevice, s);
   const std::vector<float> gtab = gelu_table();
   if (!e) e = hipMemcpyAsync(m->ws + m->off_w + kWPackedElems * 2, gtab.data(), kGeluTabBytes,
@@ -996,6 +1000,7 @@ lbm_status lbm_mlp_set_standardization(lbm_mlp *m, const float *host, void *stre
   if (!m->ws) return fail(LBM_ERR_STATE, "bind the closure first");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(m->B.stdz, host, kStdFloats * 4, hipMemcpyHostToDevice, s);
+  if (!e) e = mlp_derive(m->B, s);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(e, "mlp_set_standardization");
   return LBM_OK;

@@ -32,6 +32,7 @@ struct StepArgs {
   const void *mlp_w;              // packed bf16 weights
   const float *mlp_bias;          // b1 | b2 | b3
   const float *mlp_stdz;          // in_mean | in_inv_std | out_std | out_mean (32 each)
+  const float *mlp_s2;            // sum of out_std^2 over the 19 outputs (the judge's floor)
   unsigned long long *mlp_fallbacks;  // voxels that fell back to the regularized operator (64-bit)
   float mlp_judge;                // relative L2 tolerance against the regularized f1 (0 = off)
   // bitmask-based grouping
@@ -90,6 +91,7 @@ struct MlpBuffers {
   void *wpacked;      // packed bf16 weights
   float *bias;        // b1 | b2 | b3 (padded)
   float *stdz;        // standardization, 4 x 32
+  float *s2;          // sum of out_std^2, derived from stdz by mlp_derive whenever stdz changes
   unsigned long long *fallbacks;
   float *save;        // [batch_max][288] forward intermediates
   float *dyt;         // [batch_max][19]
@@ -103,6 +105,8 @@ struct MlpBuffers {
 LBM_NAMESPACE_K19 {  // D3Q19 only
 hipError_t mlp_pack(const MlpBuffers &B, hipStream_t s);
 hipError_t mlp_fit_standardization(const MlpBuffers &B, const float *f, int64_t n, hipStream_t s);
+// the values derived from the standardization (B.s2)
+hipError_t mlp_derive(const MlpBuffers &B, hipStream_t s);
 hipError_t mlp_forward(const MlpBuffers &B, const float *f, int64_t n, float *y, hipStream_t s);
 hipError_t mlp_gradients(const MlpBuffers &B, const float *f, const int64_t *idx, int64_t n, double *loss,
                          hipStream_t s);

@@ -428,6 +428,13 @@ __global__ void k_stats_final(const double *partial, int nblk, int64_t n, float 
   stdz[96 + i] = (float)mt;
 }
 
+// sum of out_std^2 in the order of s2_of, for the solver's judge
+__global__ void k_mlp_derive(const float *stdz, float *s2) {
+  float v = 0.0f;
+  for (int i = 0; i < Q; ++i) v = fmaf(stdz[64 + i], stdz[64 + i], v);
+  *s2 = v;
+}
+
 // ---------------------------------------------------------------- launch --
 static int64_t waves_blocks(int64_t n) { return (n + 255) / 256; }
 
@@ -440,6 +447,11 @@ hipError_t mlp_fit_standardization(const MlpBuffers &B, const float *f, int64_t 
   const int nblk = 64;
   hipLaunchKernelGGL(k_stats_partial, dim3(nblk), dim3(256), 0, s, f, n, B.partial);
   hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(32), 0, s, B.partial, nblk, n, B.stdz);
+  return mlp_derive(B, s);
+}
+
+hipError_t mlp_derive(const MlpBuffers &B, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_derive, dim3(1), dim3(1), 0, s, (const float *)B.stdz, B.s2);
   return hipGetLastError();
 }
 

@@ -134,7 +134,9 @@ __global__ __launch_bounds__(256) void k_block_interior_bits(StepArgs a, int32_t
 // order term so that the sum lands in the edge neighbour's block.  All of it
 // is taken modulo 2^32, and the true offset is below 2^32.  One AND and one
 // add per crossed face replace the 64-bit slot arithmetic, which keeps the
-// vector-instruction count of the issue-bound closure kernel down.
+// vector-instruction count of the issue-bound closure kernel down.  (The
+// HBM-bound interior kernels keep the 64-bit form: the 32-bit one, built for
+// them too, left their whole steps unchanged within 1.5%.)
 struct LaneFaces {
   uint32_t x0, x3, y0, y3, z0, z3;  // all ones where the lane sits on that face of its block
   template <int C> __device__ __forceinline__ uint32_t x() const { return C > 0 ? x0 : x3; }
@@ -146,6 +148,15 @@ __device__ __forceinline__ LaneFaces lane_faces(int lane) {
   const auto all = [](bool c) { return c ? ~0u : 0u; };
   return {all((lane & 3) == 0), all((lane & 3) == 3), all((lane & 12) == 0),
           all((lane & 12) == 12), all(lane < 16), all(lane >= 48)};
+}
+
+// if_set where the lane's bit of the wave-uniform mask is set, else if_clear:
+// one select that reads the mask from its scalar registers (as C++ the test
+// of bit `lane` becomes a 64-bit shift, an AND and a compare per direction)
+__device__ __forceinline__ uint32_t lane_select(uint64_t mask, uint32_t if_set, uint32_t if_clear) {
+  uint32_t r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
+  return r;
 }
 
 // byte offset of lane's pull source in direction I; `base` = S (lane + Q 64 own)
@@ -223,9 +234,7 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
     static_for<1, Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       uint32_t off = pull_off32<i, S>(base, lf, b, nbv);
-      if constexpr (MASKED) {
-        if ((bm[i - 1] >> lane) & 1ull) off = base + (uint32_t)(kOpp[i] * 64 * S);
-      }
+      if constexpr (MASKED) off = lane_select(bm[i - 1], base + (uint32_t)(kOpp[i] * 64 * S), off);
       raw[i] = *(const T *)(src8 + off);
     });
   } else {
@@ -258,7 +267,7 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
   const float *sd = a.mlp_stdz;
   const float ir = 1.0f / m.rho;
   float x[Q];
-  bool out_of_range = false;
+  float xmax = 0.0f;  // largest |x_i|: one max per input instead of a compare
   {
     float heq[Q];
     equilibrium(m, heq);
@@ -266,9 +275,10 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
     for (int i = 0; i < Q; ++i) {
       const float g = (h[i] - heq[i]) * ir;
       x[i] = fluid ? (g - sd[i]) * sd[32 + i] : 0.0f;
-      out_of_range = out_of_range || fabsf(x[i]) > 8.0f;
+      xmax = fmaxf(xmax, fabsf(x[i]));
     }
   }
+  const bool out_of_range = xmax > 8.0f;
   float pneq[6];
   neq_stress(h, m, pneq);
   float y[Q];
@@ -293,10 +303,7 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
     }
     const float d2 = hermite2_norm2(ds[0], ds[1], ds[2], ds[3], ds[4], ds[5]);
     const float t2 = hermite2_norm2(ps[0], ps[1], ps[2], ps[3], ps[4], ps[5]);
-    float s2 = 0.0f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) s2 = fmaf(sd[64 + i], sd[64 + i], s2);
-    off = d2 > a.mlp_judge * a.mlp_judge * (t2 + s2);
+    off = d2 > a.mlp_judge * a.mlp_judge * (t2 + *a.mlp_s2);  // s2: sum of out_std^2, kept beside stdz
   }
   float heq[Q];
   equilibrium(m, heq);
@@ -307,7 +314,9 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
     h[i] = fmaf(r, y[i], heq[i]);
     // w_i + h_i < 0 in FP32 exactly when h_i < -w_i: the rounded sum keeps
     // the sign of the exact one, which is a multiple of h_i's unit in the
-    // last place and so never underflows
+    // last place and so never underflows.  (A minimum per weight class and
+    // three compares issue fewer instructions but measured 3-5% slower: the
+    // chains of minima sit on the path to the stores.)
     negative = negative || (h[i] < -weight_f(i));
   }
   const bool fb = fluid && (out_of_range || negative || off);
