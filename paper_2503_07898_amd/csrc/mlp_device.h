@@ -355,12 +355,16 @@ __device__ __forceinline__ void mlp_forward_wave_reg(const float (&x)[Q], float 
 }
 
 // Copies the packed weights and the GELU table (20 KB) from global memory to
-// LDS (wl holds kWStageElems); every thread of the workgroup must call it
-// before any wave returns.
-__device__ __forceinline__ void stage_weights(__bf16 *wl, const __bf16 *wg) {
+// LDS (wl holds kWStageElems), and with bl the biases b1|b2|b3 too (bl holds
+// kBiasFloats); every thread of the workgroup must call it before any wave
+// returns.
+__device__ __forceinline__ void stage_weights(__bf16 *wl, const __bf16 *wg, float *bl = nullptr,
+                                              const float *bg = nullptr) {
   const uint4 *src = (const uint4 *)wg;
   uint4 *dst = (uint4 *)wl;
   for (int k = threadIdx.x; k < kWStageElems / 8; k += blockDim.x) dst[k] = src[k];
+  if (bl)
+    for (int k = threadIdx.x; k < kBiasFloats; k += blockDim.x) bl[k] = bg[k];
   __syncthreads();
 }
 

@@ -194,24 +194,18 @@ __device__ __forceinline__ uint32_t pull_off32(uint32_t base, const LaneFaces &l
 // to zero mass and momentum, and falls back per voxel to the regularized
 // operator when a standardized input leaves [-8, 8], a population turns
 // negative, or the closure's non-equilibrium part strays more than the
-// judge tolerance from the regularized operator's.  The packed weights and
-// the GELU table are staged in LDS once per workgroup.  Three waves per SIMD
-// (at most 168 registers): the network's accumulators then stay in ordinary
-// registers (no accumulator-register reads) and a third wave hides more of
-// the LDS and matrix-core latency.
+// judge tolerance from the regularized operator's.  The packed weights, the
+// GELU table and the biases are staged in LDS once per workgroup.  Three
+// waves per SIMD (at most 168 registers): the network's accumulators then
+// stay in ordinary registers (no accumulator-register reads) and a third
+// wave hides more of the LDS and matrix-core latency.
+
+// The pulls of block b (wave-uniform) into raw, issued without waiting.
 // NARROW: population buffers of at most 4 GiB (32-bit pull offsets).
 template <class ST, bool MASKED, bool NARROW>
-__global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32_t g0, int32_t n) {
+__device__ __forceinline__ void closure_gather(const StepArgs &a, int b, int lane, typename ST::T (&raw)[Q]) {
   using T = typename ST::T;
-  __shared__ __attribute__((aligned(16))) __bf16 wl[kWStageElems];
-  stage_weights(wl, (const __bf16 *)a.mlp_w);
-  const int wg = xcd_remap(blockIdx.x);
-  const int wave = threadIdx.x >> 6;
-  const int b = __builtin_amdgcn_readfirstlane(g0 + wg * 4 + wave);
-  if (b >= g0 + n) return;
-  const int lane = threadIdx.x & 63;
   const T *__restrict__ src = (const T *)a.src;
-  T *__restrict__ dst = (T *)a.dst;
   const uint32_t own_slot = (uint32_t)b * 64u + (uint32_t)lane;
   int32_t nbv[kNbr];
 #pragma unroll
@@ -224,7 +218,6 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
   // all stored values first, then their decoding: under the register limit
   // of three waves per SIMD this keeps the 19 loads of 16-bit storage in
   // flight together instead of one converted value at a time
-  T raw[Q];
   if constexpr (NARROW) {
     constexpr int S = (int)sizeof(T);
     const LaneFaces lf = lane_faces(lane);
@@ -252,6 +245,14 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
       raw[i] = src[pidx(plane, slot)];
     });
   }
+}
+
+// The closure update of block b from its pulled populations raw.
+template <class ST, bool MASKED>
+__device__ __forceinline__ void closure_update(const StepArgs &a, int b, int lane, const typename ST::T (&raw)[Q],
+                                               const __bf16 *wl, const float *bl) {
+  using T = typename ST::T;
+  T *__restrict__ dst = (T *)a.dst;
   float h[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) h[i] = ST::decode(raw[i]);
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
   float pneq[6];
   neq_stress(h, m, pneq);
   float y[Q];
-  mlp_forward_wave_reg(x, y, wl, a.mlp_bias, lane);
+  mlp_forward_wave_reg(x, y, wl, bl, lane);
 #pragma unroll
   for (int i = 0; i < Q; ++i) y[i] = fmaf(y[i], sd[64 + i], sd[96 + i]);
   float ys[6];  // second-order Hermite coordinates of the closure's output
@@ -333,6 +334,40 @@ __global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32
   T *dstb = dst + (size_t)b * (Q * 64);  // the block's rows, from a wave-uniform base
 #pragma unroll
   for (int i = 0; i < Q; ++i) ST::store(dstb, (size_t)(i * 64 + lane), h[i]);
+}
+
+// PB blocks per wave, the wave's k-th block being g0 + 4 PB wg + 4 k + wave
+// (the workgroup's four waves work on four consecutive blocks at a time).
+// The pulls of the next block are issued before the current block's update,
+// and nothing inside the update waits on a vector-memory load (weights,
+// table and biases come from LDS, the standardization through scalar
+// loads), so the one in-order counter of vector-memory loads does not tie
+// the update to the next block's pulls.  With 16-bit storage the compiled
+// kernel still waits for both blocks' pulls before the first network (it
+// packs the 16-bit values two to a register as they arrive), so what two
+// blocks per wave buy there is 38 pulls in flight per wave instead of 19.
+template <class ST, bool MASKED, bool NARROW, int PB>
+__global__ __launch_bounds__(256, 3) void k_block_interior_mlp(StepArgs a, int32_t g0, int32_t n) {
+  using T = typename ST::T;
+  __shared__ __attribute__((aligned(16))) __bf16 wl[kWStageElems];
+  // the biases sit in LDS as well: a global load inside the network would
+  // make its wait (one in-order counter) wait for the next block's pulls too
+  __shared__ __attribute__((aligned(16))) float bl[kBiasFloats];
+  stage_weights(wl, (const __bf16 *)a.mlp_w, bl, a.mlp_bias);
+  const int wg = xcd_remap(blockIdx.x);
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int b0 = __builtin_amdgcn_readfirstlane(g0 + wg * 4 * PB + wave);
+  if (b0 >= g0 + n) return;
+  T raw[2][Q];
+  closure_gather<ST, MASKED, NARROW>(a, b0, lane, raw[0]);
+#pragma unroll
+  for (int k = 0; k < PB; ++k) {
+    const int b = b0 + 4 * k;
+    if (k + 1 < PB && b + 4 < g0 + n) closure_gather<ST, MASKED, NARROW>(a, b + 4, lane, raw[(k + 1) & 1]);
+    closure_update<ST, MASKED>(a, b, lane, raw[k & 1], wl, bl);
+    if (b + 4 >= g0 + n) break;
+  }
 }
 
 #endif  // LBM_Q27
@@ -813,15 +848,21 @@ template <class ST>
 static hipError_t launch_mlp(const Launch &L, hipStream_t s) {
   const int32_t g0 = L.first, n = L.count;
   if (n <= 0) return hipSuccess;
-  const dim3 grd(xcd_grid((n + 3) / 4)), blk(256);
+  const dim3 blk(256);
   // 32-bit pull offsets while a population buffer spans at most 4 GiB
   const bool narrow = (uint64_t)L.args.S * Q * sizeof(typename ST::T) <= (1ull << 32) && !L.wide;
   if (L.kind == kKernelFull) {
-    if (narrow) hipLaunchKernelGGL((k_block_interior_mlp<ST, false, true>), grd, blk, 0, s, L.args, g0, n);
-    else hipLaunchKernelGGL((k_block_interior_mlp<ST, false, false>), grd, blk, 0, s, L.args, g0, n);
-  } else {
-    if (narrow) hipLaunchKernelGGL((k_block_interior_mlp<ST, true, true>), grd, blk, 0, s, L.args, g0, n);
-    else hipLaunchKernelGGL((k_block_interior_mlp<ST, true, false>), grd, blk, 0, s, L.args, g0, n);
+    // two blocks per wave with 16-bit storage (measured +8%); a second FP32
+    // block's pulls do not fit beside the network in the registers of three
+    // waves per SIMD (spills: 9% slower)
+    constexpr int PB = sizeof(typename ST::T) == 2 ? 2 : 1;
+    const dim3 grd(xcd_grid((n + 4 * PB - 1) / (4 * PB)));
+    if (narrow) hipLaunchKernelGGL((k_block_interior_mlp<ST, false, true, PB>), grd, blk, 0, s, L.args, g0, n);
+    else hipLaunchKernelGGL((k_block_interior_mlp<ST, false, false, PB>), grd, blk, 0, s, L.args, g0, n);
+  } else {  // the masked kernels hold bounce masks too: one block per wave
+    const dim3 grd(xcd_grid((n + 3) / 4));
+    if (narrow) hipLaunchKernelGGL((k_block_interior_mlp<ST, true, true, 1>), grd, blk, 0, s, L.args, g0, n);
+    else hipLaunchKernelGGL((k_block_interior_mlp<ST, true, false, 1>), grd, blk, 0, s, L.args, g0, n);
   }
   return hipGetLastError();
 }
