@@ -293,14 +293,18 @@ def main(argv=None) -> int:
                     "hbm_frac": round(ups * bytes_per_update / t / 1e9 / HBM_PEAK_GBS, 4),
                     "mfma_TFLOPs_bf16": round(ups * MLP_MFMA_FLOPS / t / 1e12, 1),
                     "mfma_frac": round(ups * MLP_MFMA_FLOPS / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
-                # the binding resource of the closure: vector-instruction issue
-                # (one wave per block), from the counted instructions per wave
-                kname = f"lbm::k19::k_block_interior_mlp<lbm::k19::{STORE_NAME[interior]}, false, true>"
+                # the binding resource of the closure: vector-instruction issue,
+                # from the counted instructions per wave (a wave takes one block
+                # with FP32 storage, two with 16-bit storage)
+                pb = 1 if interior == lbm.F32 else 2
+                kname = f"lbm::k19::k_block_interior_mlp<lbm::k19::{STORE_NAME[interior]}, false, true, {pb}>"
                 vpw = measured_valu(kname)
+                waves = (int(nf) + pb - 1) // pb
                 il = arms[name]["interior_launch"]
                 il["valu_insts_per_wave"] = vpw
-                il["valu_lane_Tops"] = None if vpw is None else round(vpw * 64 * int(nf) / t / 1e12, 2)
-                il["valu_frac"] = None if vpw is None else round(vpw * 64 * int(nf) / t / VALU_LANE_PEAK, 4)
+                il["blocks_per_wave"] = pb
+                il["valu_lane_Tops"] = None if vpw is None else round(vpw * 64 * waves / t / 1e12, 2)
+                il["valu_frac"] = None if vpw is None else round(vpw * 64 * waves / t / VALU_LANE_PEAK, 4)
                 il["bound"] = "valu"
             gg.close()
             torch.cuda.empty_cache()
