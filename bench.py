@@ -374,6 +374,8 @@ def main(argv=None) -> int:
             return g
 
         for name, make in (("taylor_green256_re1600_f32_mlp", lambda: cases.taylor_green()),
+                           ("taylor_green256_re1600_f16_mlp",
+                            lambda: cases.taylor_green(storage=lbm.F16_SHIFTED)),
                            ("cavity256_f32_mlp", lambda: cases.cavity()),
                            ("cavity256_f16_mlp", lambda: cases.cavity(storage=lbm.F16_SHIFTED))):
             net.fallbacks(reset=True)
