@@ -198,10 +198,10 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--arms", default="all", choices=["all", "none", "closure", "storage", "table"],
+    ap.add_argument("--arms", default="all", choices=["all", "none", "closure", "storage", "tunnel", "table"],
                     help="closure: only the learned-closure arms; storage: only the 16-bit cavity "
-                         "arms (both for counter runs); table: the 320^3 and 480^3 multires "
-                         "cavity rows of table multiResLbm")
+                         "arms; tunnel: only the D3Q19 wind-tunnel arms (these three for counter "
+                         "runs); table: the 320^3 and 480^3 multires cavity rows of table multiResLbm")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (torch) 5 times, the reference "
@@ -265,7 +265,7 @@ def main(argv=None) -> int:
     torch.cuda.empty_cache()
 
     arms = {}
-    if args.arms in ("all", "closure", "storage", "table"):
+    if args.arms in ("all", "closure", "storage", "tunnel", "table"):
         def arm(name, make, steps, bytes_per_update, interior=None):
             log(name)
             gg = make()
@@ -316,11 +316,13 @@ def main(argv=None) -> int:
         arm("cavity256_f32_plain_lexicographic", lambda: cases.cavity(schedule=lbm.PLAIN_SINGLE_KERNEL), 100, 152)
         arm("cavity256_f16_disagg", lambda: cases.cavity(storage=lbm.F16_SHIFTED), 100, 76)
         arm("cavity256_bf16_disagg", lambda: cases.cavity(storage=lbm.BF16_SHIFTED), 100, 76)
+    if args.arms in ("all", "tunnel"):
         for st, bpu in ((lbm.F32, 152), (lbm.F16_SHIFTED, 76)):
             for sch, nm in ((lbm.PLAIN_SINGLE_KERNEL, "naive_single_kernel"), (lbm.DISAGG, "disagg_grouped"),
                             (lbm.DISAGG_BITMASK, "disagg_bitmask")):
                 arm(f"tunnel512x256x256_{['f32', 'f16'][st]}_{nm}",
                     lambda st=st, sch=sch: cases.tunnel(storage=st, schedule=sch), 50, bpu)
+    if args.arms == "all":
         # multires schedules: the unfused baseline, the paper's own (uniform
         # blocks fused, jump blocks unfused) and every group fused
         mr_schedules = ((lbm.PLAIN_SINGLE_KERNEL, "unfused_baseline"),
